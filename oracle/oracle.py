@@ -1,0 +1,222 @@
+"""Python glue for the CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg may import this module; the solver never does.  It shares no
+code with the GPU library.
+
+Public spectra here use the half-spectrum (R2C) layout [3][N][N][N/2+1] of a
+real field u[3][z][y][x], i.e. numpy.fft.rfftn(u, axes=(-3,-2,-1),
+norm="forward").  The C oracle works on full complex N^3 spectra; the helpers
+below only convert layouts (Hermitian extension, slicing).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so (plain gcc, OpenMP over lines)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("s", ctypes.c_double), ("m_cut", ctypes.c_double),
+                ("q_kind", ctypes.c_int), ("theta", ctypes.c_double), ("kcut", ctypes.c_int)]
+
+
+@dataclass
+class Params:
+    """Model parameters of eqs. (2.1)-(2.4).  eps/m_cut < 0 select the
+    defaults eps_N = 1e-3 (32/N)^(2s-1) and m_N = N/3; kcut < 0 selects the
+    2/3-rule cutoff floor((N-1)/3)."""
+    eps: float = -1.0
+    s: float = 1.5
+    m_cut: float = -1.0
+    q_kind: int = 0
+    theta: float = 1.0
+    kcut: int = -1
+
+    def resolved(self, n: int) -> "Params":
+        eps = self.eps if self.eps >= 0 else 1e-3 * (32.0 / n) ** (2.0 * self.s - 1.0)
+        m = self.m_cut if self.m_cut >= 0 else n / 3.0
+        return Params(eps, self.s, m, self.q_kind, self.theta, self.kcut)
+
+    def c(self, n: int) -> _Params:
+        r = self.resolved(n)
+        return _Params(r.eps, r.s, r.m_cut, r.q_kind, r.theta, r.kcut)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        P = ctypes.c_void_p
+        I = ctypes.c_int
+        D = ctypes.c_double
+        pp = ctypes.POINTER(_Params)
+        sig = {
+            "orc_dft1": (None, [I, P, P, I]),
+            "orc_fft3": (None, [I, P, I]),
+            "orc_dft3_brute": (None, [I, P, P, I]),
+            "orc_project": (None, [I, pp, P]),
+            "orc_forward": (None, [I, P, P]),
+            "orc_inverse": (D, [I, I, P, P]),
+            "orc_rhs": (D, [I, pp, P, P]),
+            "orc_ssprk3": (None, [I, pp, P, D, I]),
+            "orc_rhs_vjp": (None, [I, pp, P, P, P]),
+            "orc_adjoint_step": (None, [I, pp, P, D, P]),
+            "orc_energy_spectrum": (None, [I, P, P, I]),
+            "orc_div_rel": (D, [I, P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(_lib, name)
+            f.restype = res
+            f.argtypes = args
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------- layouts
+def full_from_r2c(h: np.ndarray, n: int) -> np.ndarray:
+    """Hermitian extension of a half spectrum [..., N, N, N/2+1] to the full
+    [..., N, N, N] spectrum: X[kz,ky,kx] = conj(X[-kz,-ky,-kx]) for kx > N/2."""
+    h = np.asarray(h, dtype=np.complex128)
+    out = np.zeros(h.shape[:-1] + (n,), dtype=np.complex128)
+    nh = n // 2 + 1
+    out[..., :nh] = h
+    iz = (-np.arange(n)) % n
+    for kx in range(nh, n):
+        plane = h[..., :, :, n - kx]
+        out[..., kx] = np.conj(plane[..., iz, :][..., :, iz])
+    return np.ascontiguousarray(out)
+
+
+def r2c_from_full(f: np.ndarray, n: int) -> np.ndarray:
+    return np.ascontiguousarray(f[..., : n // 2 + 1])
+
+
+# ---------------------------------------------------------------- transforms
+def dft1(x: np.ndarray, sign: int) -> np.ndarray:
+    """Unnormalised 1-D DFT by the oracle's recursive mixed-radix routine."""
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    out = np.empty_like(x)
+    lib().orc_dft1(x.size, _ptr(x), _ptr(out), sign)
+    return out
+
+
+def fft3(a: np.ndarray, sign: int) -> np.ndarray:
+    """Unnormalised 3-D DFT of an N^3 complex array (recursive, per axis)."""
+    a = np.array(a, dtype=np.complex128, order="C", copy=True)
+    lib().orc_fft3(a.shape[0], _ptr(a), sign)
+    return a
+
+
+def dft3_brute(a: np.ndarray, sign: int) -> np.ndarray:
+    """The 3-D DFT summed from its definition, O(N^6)."""
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    out = np.empty_like(a)
+    lib().orc_dft3_brute(a.shape[0], _ptr(a), _ptr(out), sign)
+    return out
+
+
+def forward(u: np.ndarray) -> np.ndarray:
+    """Physical real [3][N]^3 -> normalised half spectrum (no truncation)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    n = u.shape[-1]
+    full = np.empty(u.shape, dtype=np.complex128)
+    lib().orc_forward(n, _ptr(u), _ptr(full))
+    return r2c_from_full(full, n)
+
+
+def inverse(uh: np.ndarray, n: int) -> np.ndarray:
+    """Half spectrum [c][N][N][N/2+1] -> physical real [c][N]^3."""
+    full = full_from_r2c(uh, n)
+    nc = full.shape[0]
+    u = np.empty((nc, n, n, n), dtype=np.float64)
+    lib().orc_inverse(n, nc, _ptr(full), _ptr(u))
+    return u
+
+
+# ---------------------------------------------------------------- the method
+def project(uh: np.ndarray, n: int, prm: Params = Params()) -> np.ndarray:
+    """T P u-hat: 2/3 truncation and Leray projection."""
+    full = full_from_r2c(uh, n)
+    c = prm.c(n)
+    lib().orc_project(n, ctypes.byref(c), _ptr(full))
+    return r2c_from_full(full, n)
+
+
+def initial_state(u0: np.ndarray, prm: Params = Params()) -> np.ndarray:
+    """u-hat(0) = T P F[u0] from a physical field (eq. (2.1), third line)."""
+    n = u0.shape[-1]
+    return project(forward(u0), n, prm)
+
+
+def rhs(uh: np.ndarray, n: int, prm: Params = Params()) -> np.ndarray:
+    """One evaluation of the SHV right-hand side F(u-hat)."""
+    full = full_from_r2c(uh, n)
+    out = np.empty_like(full)
+    c = prm.c(n)
+    lib().orc_rhs(n, ctypes.byref(c), _ptr(full), _ptr(out))
+    return r2c_from_full(out, n)
+
+
+def ssprk3(uh: np.ndarray, n: int, dt: float, nsteps: int, prm: Params = Params()) -> np.ndarray:
+    full = full_from_r2c(uh, n)
+    c = prm.c(n)
+    lib().orc_ssprk3(n, ctypes.byref(c), _ptr(full), float(dt), int(nsteps))
+    return r2c_from_full(full, n)
+
+
+def rhs_vjp(uh: np.ndarray, lam: np.ndarray, n: int, prm: Params = Params()) -> np.ndarray:
+    """F'(u-hat)^T lambda in the full-spectrum inner product Re sum conj(a) b."""
+    fu = full_from_r2c(uh, n)
+    fl = full_from_r2c(lam, n)
+    out = np.empty_like(fu)
+    c = prm.c(n)
+    lib().orc_rhs_vjp(n, ctypes.byref(c), _ptr(fu), _ptr(fl), _ptr(out))
+    return r2c_from_full(out, n)
+
+
+def adjoint_step(uh: np.ndarray, lam: np.ndarray, n: int, dt: float, prm: Params = Params()) -> np.ndarray:
+    """dJ/du^{n+1} -> dJ/du^n through one SSP-RK3 step taken from u^n = uh."""
+    fu = full_from_r2c(uh, n)
+    fl = full_from_r2c(lam, n)
+    c = prm.c(n)
+    lib().orc_adjoint_step(n, ctypes.byref(c), _ptr(fu), float(dt), _ptr(fl))
+    return r2c_from_full(fl, n)
+
+
+def energy_spectrum(uh: np.ndarray, n: int, nbins: int) -> np.ndarray:
+    full = full_from_r2c(uh, n)
+    E = np.zeros(nbins, dtype=np.float64)
+    lib().orc_energy_spectrum(n, _ptr(full), _ptr(E), nbins)
+    return E
+
+
+def div_rel(uh: np.ndarray, n: int) -> float:
+    full = full_from_r2c(uh, n)
+    return float(lib().orc_div_rel(n, _ptr(full)))
+
+
+def kcut(n: int) -> int:
+    return (n - 1) // 3

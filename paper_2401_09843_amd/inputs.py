@@ -1,0 +1,138 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the bench.
+
+This module only draws and tabulates input fields on the grid; it contains
+none of the solver's arithmetic (no truncation, projection, right-hand side
+or time stepping).  Both the GPU path and the CPU oracle receive the arrays
+made here.
+
+Fields are physical real arrays u[3][z][y][x] on the grid x_j = 2*pi*j/N of
+the periodic box [0, 2*pi]^3.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def grid(n: int):
+    x = 2.0 * np.pi * np.arange(n) / n
+    z, y, xx = np.meshgrid(x, x, x, indexing="ij")
+    return xx, y, z
+
+
+def taylor_green(n: int) -> np.ndarray:
+    """u = (sin x cos y cos z, -cos x sin y cos z, 0)."""
+    x, y, z = grid(n)
+    u = np.zeros((3, n, n, n))
+    u[0] = np.sin(x) * np.cos(y) * np.cos(z)
+    u[1] = -np.cos(x) * np.sin(y) * np.cos(z)
+    return u
+
+
+def taylor_green_2d(n: int) -> np.ndarray:
+    """The z-independent field (sin x cos y, -cos x sin y, 0)."""
+    x, y, z = grid(n)
+    u = np.zeros((3, n, n, n))
+    u[0] = np.sin(x) * np.cos(y)
+    u[1] = -np.cos(x) * np.sin(y)
+    return u
+
+
+def abc_flow(n: int, k0: int = 1, A: float = 1.0, B: float = 1.0, C: float = 1.0) -> np.ndarray:
+    """Arnold-Beltrami-Childress field at wavenumber k0 (curl u = k0 u)."""
+    x, y, z = grid(n)
+    u = np.empty((3, n, n, n))
+    u[0] = A * np.sin(k0 * z) + C * np.cos(k0 * y)
+    u[1] = B * np.sin(k0 * x) + A * np.cos(k0 * z)
+    u[2] = C * np.sin(k0 * y) + B * np.cos(k0 * x)
+    return u
+
+
+def helical_mode(n: int, k=(7, 7, 7), amp: float = 1.0, phase: float = 0.3) -> np.ndarray:
+    """Single helical (Beltrami) Fourier mode: u = Re[h exp(i k.x + i phase)]
+    with h = a + i (k/|k|) x a, a a unit vector orthogonal to k, so that
+    curl u = |k| u and the nonlinear term is a pure gradient."""
+    kv = np.asarray(k, dtype=np.float64)
+    kn = kv / np.linalg.norm(kv)
+    t = np.array([1.0, 0.0, 0.0]) if abs(kn[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    a = np.cross(kn, t)
+    a /= np.linalg.norm(a)
+    b = np.cross(kn, a)
+    x, y, z = grid(n)
+    th = kv[0] * x + kv[1] * y + kv[2] * z + phase
+    u = np.empty((3, n, n, n))
+    for c in range(3):
+        u[c] = amp * (a[c] * np.cos(th) - b[c] * np.sin(th))
+    return u
+
+
+def shear_profile(y: np.ndarray, rho: float) -> np.ndarray:
+    """Doubly periodic shear layer: tanh((y-pi/2)/rho) for y < pi and
+    tanh((3pi/2-y)/rho) for y >= pi."""
+    return np.where(y < np.pi, np.tanh((y - np.pi / 2) / rho), np.tanh((1.5 * np.pi - y) / rho))
+
+
+def draw_modes(rng: np.random.Generator, nmodes: int = 16, kmax: float = 4.0):
+    """nmodes random Fourier modes: wave vector k uniform over the integer
+    vectors with 0 < |k| <= kmax, unit amplitude vector a orthogonal to k
+    (uniform angle), phase uniform in [0, 2 pi)."""
+    r = int(np.floor(kmax))
+    cand = np.array([(i, j, l) for i in range(-r, r + 1) for j in range(-r, r + 1) for l in range(-r, r + 1)
+                     if 0 < i * i + j * j + l * l <= kmax * kmax], dtype=np.int64)
+    modes = []
+    for _ in range(nmodes):
+        k = cand[rng.integers(len(cand))]
+        kn = k / np.linalg.norm(k)
+        t = np.array([1.0, 0.0, 0.0]) if abs(kn[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+        e1 = np.cross(kn, t)
+        e1 /= np.linalg.norm(e1)
+        e2 = np.cross(kn, e1)
+        ang = rng.uniform(0.0, 2.0 * np.pi)
+        a = np.cos(ang) * e1 + np.sin(ang) * e2
+        phi = rng.uniform(0.0, 2.0 * np.pi)
+        modes.append((k.copy(), a, phi))
+    return modes
+
+
+def shear_layer(n: int, seed: int = 0, rho: float = 0.05, delta=0.025, nmodes: int = 16, kmax: float = 4.0):
+    """Seeded perturbed doubly periodic shear layer.
+
+    delta is a number, or a (lo, hi) pair from which delta is drawn uniformly
+    first from the sample's stream.  Returns (u, delta, modes); u is not
+    projected (the solver's initial projection does that)."""
+    rng = np.random.default_rng(seed)
+    if isinstance(delta, (tuple, list)):
+        delta = float(rng.uniform(delta[0], delta[1]))
+    modes = draw_modes(rng, nmodes, kmax)
+    x, y, z = grid(n)
+    u = np.zeros((3, n, n, n))
+    u[0] = shear_profile(y, rho)
+    for k, a, phi in modes:
+        th = k[0] * x + k[1] * y + k[2] * z + phi
+        c = np.cos(th)
+        for comp in range(3):
+            u[comp] += delta * a[comp] * c
+    return u, float(delta), modes
+
+
+def cfl_dt(u: np.ndarray, cfl: float = 0.5) -> float:
+    """dt = cfl * (2 pi / N) / max_x(|u|+|v|+|w|) of the given field."""
+    n = u.shape[-1]
+    return float(cfl * (2.0 * np.pi / n) / np.max(np.abs(u).sum(axis=0)))
+
+
+def random_field(n: int, seed: int, slope: float = 1.0, ncomp: int = 3) -> np.ndarray:
+    """Seeded random real field with a decaying spectrum: Gaussian modes
+    weighted by (1 + |k|^2)^(-slope/2), tabulated on the grid."""
+    rng = np.random.default_rng(seed)
+    k1 = np.fft.fftfreq(n, 1.0 / n)
+    kz, ky, kx = np.meshgrid(k1, k1, k1, indexing="ij")
+    w = (1.0 + kx * kx + ky * ky + kz * kz) ** (-slope / 2.0)
+    spec = (rng.standard_normal((ncomp, n, n, n)) + 1j * rng.standard_normal((ncomp, n, n, n))) * w
+    u = np.fft.ifftn(spec, axes=(-3, -2, -1)).real
+    return u / np.sqrt(np.mean(u * u))
+
+
+def half_spectrum(u: np.ndarray) -> np.ndarray:
+    """numpy's normalised half spectrum of a real field (the solver's public
+    layout): rfftn(u, norm="forward") over the last three axes."""
+    return np.fft.rfftn(u, axes=(-3, -2, -1), norm="forward")
