@@ -1,0 +1,151 @@
+"""Benchmark: SSP-RK3 steps of the spectral hyperviscosity solver on one MI355X.
+
+Default workload: the seeded perturbed shear layer at N = 1024^3, FP32, s = 1.5,
+step multiplier at m_N = N/3, eps_N = 1e-3 (32/N)^2, dt from CFL 0.5; W warm-up
+steps, then K timed steps (one ns_step call, graph replay), inputs resident in
+HBM.  Prints one JSON line with Mpts*RK-steps/s, the HBM roofline of the
+dominant pass (algorithmic bytes / live HIP-event duration) and the CPU
+oracle timed on a bounded sample of the same workload family.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 2] [--n 1024]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def cpu_baseline(n_sample: int = 128):
+    """The oracle (FP64, all host cores) for one SSP-RK3 step of the same
+    shear-layer family at n_sample^3; returns Mpts*RK-steps/s."""
+    from oracle import oracle as orc
+    from paper_2401_09843_amd import inputs
+
+    u0, _, _ = inputs.shear_layer(n_sample, seed=0)
+    dt = inputs.cfl_dt(u0)
+    uh = orc.initial_state(u0)
+    t0 = time.perf_counter()
+    orc.ssprk3(uh, n_sample, dt, 1)
+    t = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n_sample ** 3 / t / 1e6, "unit": "Mpts*RK-steps/s", "cores": cores, "kind": "oracle",
+            "sample": "one SSP-RK3 step (3 RHS) of the seed-0 shear layer at %d^3, FP64, %.1f s" % (n_sample, t)}
+
+
+def measured_traffic(kernel: str, n: int):
+    """HBM bytes per launch from committed rocprofv3 PMC summaries, if any."""
+    path = os.path.join(PROFILE_DIR, "traffic_%s_n%d.json" % (kernel, n))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    return d.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--dtype", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2401_09843_amd import inputs, ns, perfmodel
+
+    n = args.n
+    dt_torch = torch.float32 if args.dtype == "fp32" else torch.float64
+    rbytes = 4 if args.dtype == "fp32" else 8
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    print("bench: n=%d %s steps=%d warmup=%d" % (n, args.dtype, args.steps, args.warmup), file=sys.stderr, flush=True)
+
+    S = ns.Solver(n, dtype=dt_torch, graph=True)
+    u0, _, _ = inputs.shear_layer_torch(n, seed=0, device=dev, dtype=dt_torch)
+    dt = float(0.5 * (2.0 * 3.141592653589793 / n) / u0.abs().sum(dim=0).max().item())
+    uh = S.forward(u0)
+    del u0
+    torch.cuda.synchronize()
+    print("bench: initial state ready, dt=%.3e" % dt, file=sys.stderr, flush=True)
+
+    if args.warmup > 0:
+        S.step(uh, dt, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.step(uh, dt, args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    ms_per_step = wall / args.steps * 1e3
+    value = n ** 3 * args.steps / wall / 1e6
+    print("bench: timed %.3f s, %.2f ms/step" % (wall, ms_per_step), file=sys.stderr, flush=True)
+
+    roofline = None
+    per_pass = {}
+    if not args.no_profile:
+        S.profile(True)
+        S.step(uh, dt, args.steps)
+        prof = S.profile_read()
+        S.profile(False)
+        bpl = perfmodel.pass_bytes_per_launch(n, rbytes)
+        for name, (ms, cnt) in prof.items():
+            if cnt:
+                avg = ms / cnt
+                per_pass[name] = {"avg_ms": avg, "launches": cnt, "GBps": bpl[name] / (avg * 1e-3) / 1e9}
+        dom = max(per_pass, key=lambda k: per_pass[k]["avg_ms"] * per_pass[k]["launches"])
+        ach = per_pass[dom]["GBps"]
+        traffic = measured_traffic(dom, n)
+        roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                    "traffic": traffic, "kernel": dom, "algorithmic_bytes_per_launch": bpl[dom]}
+    step_bytes = perfmodel.step_bytes(n, rbytes)
+    finite = bool(torch.isfinite(torch.view_as_real(uh)).all().item())
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline()
+
+    out = {
+        "metric": "Mpts*RK-steps/s (SSP-RK3, spectral hyperviscosity NS, 2/3 dealiased)",
+        "value": value,
+        "unit": "Mpts*RK-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.dtype == "fp32" else "f64",
+        "data": "synthetic: seeded perturbed doubly periodic shear layer (rho=0.05, delta=0.025, 16 modes |k|<=4)",
+        "config": {"workload": "shear-layer SSP-RK3 N=%d^3 %s, CFL 0.5, s=1.5, m_N=N/3" % (n, args.dtype),
+                   "N": n, "parallelism": "single GPU"},
+        "hbm_model_bytes_per_step": step_bytes,
+        "step_roofline_frac": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "roofline": roofline,
+        "passes": per_pass,
+        "finite": finite,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * ns.h - C ABI of the MI355X spectral hyperviscosity Navier-Stokes library.
+ *
+ * The library advances the semi-discrete spectral hyperviscosity (SHV)
+ * system for 3-D incompressible Navier-Stokes / Euler on the periodic box
+ * [0, 2*pi]^3 (Rohner & Mishra, PASC '24, arXiv:2401.09843, Sec. 2.2,
+ * eq. (2.1)) in Fourier space (Sec. 2.3, eq. (2.5)) with the third-order
+ * strong-stability-preserving Runge-Kutta scheme of eq. (2.6).  Every step
+ * of the computation runs in the library's own HIP kernels for gfx950.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid and transforms: x_j = 2*pi*j/N on each axis; the forward transform is
+ * normalised, u-hat_k = N^-3 sum_x u(x) exp(-i k.x).  Index j along an axis
+ * carries wavenumber j for j < N/2 and j - N otherwise.
+ *
+ * Public spectral layout ("R2C layout"): one sample's velocity spectrum is a
+ * dense device array uhat[3][N][N][N/2+1] of interleaved complex numbers
+ * (re, im) in the context's precision, component-major (u_x, u_y, u_z), then
+ * k_z index, k_y index, k_x = 0..N/2 (x fastest).  It equals
+ * numpy.fft.rfftn(u, axes=(-3,-2,-1), norm="forward") of the real field
+ * u[3][z][y][x].  Modes outside the 2/3-rule cube |k_x|,|k_y|,|k_z| <= K,
+ * K = floor((N-1)/3) (Algorithm 2, step 5; Sec. 2.2 for the cube), are
+ * ignored on input and written as zero on output.  On the k_x = 0 plane the
+ * real part of the real-space field is used, i.e. the plane is read as its
+ * Hermitian part.
+ *
+ * Physical layout: u[3][N][N][N] real, (component, z, y, x), x fastest.
+ *
+ * Batches: a context holds nsamples samples with sizes n[i].  Array
+ * arguments named "const* x" are HOST arrays of nsamples DEVICE pointers,
+ * one per sample.  Samples of equal N run in the same kernel launches.
+ *
+ * Ownership: the caller owns every state, output, tape and adjoint buffer;
+ * the context owns its plans, twiddle tables, workspaces and graphs and
+ * frees them in ns_destroy.  A context must not be used from two host
+ * threads at once.  All device work is enqueued on the stream given to
+ * ns_init; calls return without synchronising unless stated.
+ *
+ * Errors: every call returns an ns_status and never aborts.  Bad arguments
+ * give NS_ERR_ARG with nothing enqueued; the message is in ns_last_error.
+ * A failed HIP call gives NS_ERR_HIP and makes the context sticky-failed:
+ * later calls return NS_ERR_STATE.
+ */
+#ifndef NS_H
+#define NS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ns_ctx ns_ctx;
+
+typedef enum {
+    NS_OK = 0,
+    NS_ERR_ARG = 1,
+    NS_ERR_UNSUPPORTED = 2,
+    NS_ERR_OOM = 3,
+    NS_ERR_HIP = 4,
+    NS_ERR_STATE = 5,
+    NS_ERR_NONFINITE = 6
+} ns_status;
+
+typedef enum { NS_F32 = 0, NS_F64 = 1 } ns_dtype;
+
+/* flags */
+#define NS_USE_GRAPH    1u  /* replay each RK3 step from a captured hipGraph */
+#define NS_CHECK_FINITE 2u  /* ns_step checks the energy after the call */
+#define NS_NO_TUNE      4u  /* skip the autotuner; use the built-in schedules */
+
+/* Model and run parameters (eqs. (2.1)-(2.4)).
+ *   eps    epsilon_N, the hyperviscosity amplitude; < 0 selects the default
+ *          1e-3 * (32/N)^(2s-1) per sample.
+ *   s      hyperviscosity order: the damping symbol is |k|^{2s} (s >= 1).
+ *   m_cut  m_N: Q-hat_k = 0 for |k| <= m_N; < 0 selects N/3 per sample.
+ *   q_kind 0: Q-hat_k = 1 above m_N; 1: Q-hat_k = 1 - (m_N/|k|)^((2s-1)/theta)
+ *          above m_N (the lower bound of eq. (2.3)).
+ *   theta  the exponent parameter of eq. (2.4), used by q_kind 1.
+ * The right-hand side is dissipative: F_k = ... - eps |k|^{2s} Q-hat_k u-hat_k. */
+typedef struct {
+    ns_dtype       dtype;
+    int32_t        nsamples;   /* >= 1 */
+    const int32_t* n;          /* host array [nsamples]: even N, 8..1024, 2^a 3^b 5^c, and supported */
+    double         eps;
+    double         s;
+    double         m_cut;
+    int32_t        q_kind;
+    double         theta;
+    uint32_t       flags;      /* NS_USE_GRAPH | NS_CHECK_FINITE | NS_NO_TUNE */
+    const char*    tune_cache; /* autotuner cache file (JSON) or NULL */
+} ns_params;
+
+/* Create a context on the current HIP device; hip_stream is a hipStream_t
+ * (NULL = the default stream).  Allocates the workspaces; runs the
+ * autotuner for each distinct N unless NS_NO_TUNE is set. */
+ns_status ns_init(const ns_params* params, void* hip_stream, ns_ctx** out);
+
+/* Free everything the context owns.  Accepts NULL. */
+ns_status ns_destroy(ns_ctx* ctx);
+
+/* Message of the last failure on ctx (context-owned, valid until the next
+ * call); for a NULL ctx, the last ns_init failure of the calling thread. */
+const char* ns_last_error(const ns_ctx* ctx);
+
+/* Total bytes of device memory the context allocated. */
+ns_status ns_workspace_bytes(const ns_ctx* ctx, size_t* bytes);
+
+/* Supported grid sizes: writes up to cap values to sizes, count to *count. */
+ns_status ns_supported_sizes(int32_t* sizes, int32_t cap, int32_t* count);
+
+/* Initial data, eq. (2.1) third line with the divergence constraint:
+ * uhat = T P F[u], from physical u[3][N][N][N] (R2C layout out).  In- and
+ * output may not alias. */
+ns_status ns_forward(ns_ctx* ctx, const void* const* u_phys, void* const* uhat);
+
+/* Physical field u = F^-1[T uhat] (T = 2/3 truncation), real [3][N]^3. */
+ns_status ns_inverse(ns_ctx* ctx, const void* const* uhat, void* const* u_phys);
+
+/* T and the Leray projection (I - k k^T/|k|^2) in place (eq. (2.5)). */
+ns_status ns_project(ns_ctx* ctx, void* const* uhat);
+
+/* One evaluation of the right-hand side (Algorithm 2 with eq. (2.5)):
+ *   rhs = T[ P(-i k . F[u (x) u]) - eps |k|^{2s} Q-hat u-hat ],
+ * with u (x) u formed pointwise on the N^3 grid from u = F^-1[T uhat] and
+ * its transform 2/3-truncated.  uhat_in and rhs_out may not alias. */
+ns_status ns_rhs(ns_ctx* ctx, const void* const* uhat_in, void* const* rhs_out);
+
+/* nsteps SSP-RK3 steps (eq. (2.6)) of fixed size dt[i] (host array
+ * [nsamples], finite and > 0) in place on uhat.  nsteps >= 0.  With
+ * NS_CHECK_FINITE, synchronises and returns NS_ERR_NONFINITE if a sample's
+ * energy is not finite at the end. */
+ns_status ns_step(ns_ctx* ctx, void* const* uhat_inout, const double* dt, int32_t nsteps);
+
+/* Bytes of tape per sample that ns_step_taped writes for nsteps steps. */
+ns_status ns_tape_bytes(const ns_ctx* ctx, int32_t nsteps, size_t* per_sample);
+
+/* As ns_step, and also records each step's three stage states into tape[i]
+ * (opaque, ns_tape_bytes(nsteps) bytes per sample), for ns_adjoint_step. */
+ns_status ns_step_taped(ns_ctx* ctx, void* const* uhat_inout, const double* dt, int32_t nsteps,
+                        void* const* tape);
+
+/* Discrete adjoint of one SSP-RK3 step (not in the paper: the transpose of
+ * the Jacobian of the step in the inner product <a,b> = Re sum over the full
+ * spectrum of conj(a_k) b_k).  lam (R2C layout) holds dJ/du^{n+1} on entry
+ * and dJ/du^n on return.  The stage states come from tape_step[i] (one step
+ * of a tape written by ns_step_taped, i.e. tape + step * per_step_bytes) or,
+ * if tape_step is NULL, are recomputed from uhat_n (the step's input). */
+ns_status ns_adjoint_step(ns_ctx* ctx, const void* const* uhat_n, const void* const* tape_step,
+                          const double* dt, void* const* lam_inout);
+
+/* Energy spectrum (the energy-spectrum writer of Sec. 2.4):
+ * E[i][kappa] = 1/2 sum over modes of the full spectrum with
+ * round(|k|) = kappa of |u-hat_k|^2, kappa = 0..kbins-1, written as FP64
+ * into the DEVICE array E_dev[nsamples][kbins].  Deterministic. */
+ns_status ns_energy_spectrum(ns_ctx* ctx, const void* const* uhat, double* E_dev, int32_t kbins);
+
+/* Synchronise the context's stream (convenience for callers without HIP). */
+ns_status ns_sync(ns_ctx* ctx);
+
+/* Pass profiler.  With enable != 0 every pass launch of ns_rhs / ns_step is
+ * bracketed by HIP events on the context's stream (ns_step then launches
+ * eagerly instead of replaying its graph).  ns_profile_read synchronises,
+ * writes per pass p the summed device time in milliseconds ms[p] and the
+ * number of launches count[p] since the last read, and resets them.
+ * Passes: 0 = inverse z (I1), 1 = inverse y (I2), 2 = x (C2R, products,
+ * R2C), 3 = forward y (F2), 4 = forward z + epilogue (F3). */
+#define NS_NPASS 5
+ns_status ns_profile(ns_ctx* ctx, int32_t enable);
+ns_status ns_profile_read(ns_ctx* ctx, double* ms, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NS_H */

@@ -1,0 +1,281 @@
+// Device FFT engine for gfx950: small-radix DFT codelets and a register
+// Stockham (self-sorting, mixed-radix) FFT executed cooperatively by G
+// threads per line, with the stages exchanged through LDS.
+//
+// A transform of length N with radices R_0..R_{S-1} (N = prod R_s) keeps
+// E = N/G elements per thread in registers.  Before stage s (span
+// P_s = R_0...R_{s-1}) thread t holds, for each of its butterflies
+// b = t + q*G (q < N/(R_s G)), the inputs x[b + m N/R_s] (m < R_s) in
+// v[q R_s + m].  The stage multiplies input m by w_{P_s R_s}^{m (b mod P_s)},
+// applies a radix-R_s DFT and sends output m to position
+// ((b - k) R_s + k) + m P_s, k = b mod P_s (Stockham autosort order).  After
+// the last stage thread t holds X[t + q G + m N/R_last] in v[q R_last + m],
+// i.e. outputs are in natural order with no bit reversal.  Twiddles come from
+// a table tw[e] = exp(-2 pi i e / N) rounded from extended precision on the
+// host; the inverse direction uses its conjugate.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ns {
+
+template <typename R>
+struct alignas(2 * sizeof(R)) cpx {
+    R x, y;
+};
+
+template <typename R>
+__device__ __forceinline__ cpx<R> cadd(cpx<R> a, cpx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> csub(cpx<R> a, cpx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> cscale(cpx<R> a, R s) { return {a.x * s, a.y * s}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+// a * (DIR * i)
+template <int DIR, typename R>
+__device__ __forceinline__ cpx<R> mul_i(cpx<R> a)
+{
+    if constexpr (DIR > 0) return {-a.y, a.x};
+    else return {a.y, -a.x};
+}
+// a * w for DIR = -1, a * conj(w) for DIR = +1 (w from the forward table)
+template <int DIR, typename R>
+__device__ __forceinline__ cpx<R> twiddle(cpx<R> a, cpx<R> w)
+{
+    if constexpr (DIR < 0) return {a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x};
+    else return {a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y};
+}
+
+// cos and sin of 2 pi j / 16
+constexpr double kC16[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                                        0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                                        -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+                                        0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+constexpr double kS16[16] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+                                        1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                                        0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                                        -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+
+// a * exp(DIR 2 pi i e / RR) for a compile-time exponent, RR dividing 16
+template <int RR, int E, int DIR, typename R>
+__device__ __forceinline__ cpx<R> rot_const(cpx<R> a)
+{
+    constexpr int e = E % RR;
+    if constexpr (e == 0) return a;
+    else if constexpr (4 * e == RR) return mul_i<DIR>(a);
+    else if constexpr (2 * e == RR) return {-a.x, -a.y};
+    else if constexpr (4 * e == 3 * RR) return mul_i<-DIR>(a);
+    else {
+        constexpr int j = e * (16 / RR);
+        const R c = (R)kC16[j];
+        const R s = (R)(DIR * kS16[j]);
+        return {a.x * c - a.y * s, a.x * s + a.y * c};
+    }
+}
+
+// ---------------------------------------------------------------- codelets
+// In-place y[k] = sum_m v[m] exp(DIR 2 pi i m k / R).
+template <int R, int DIR, typename T>
+struct Dft;
+
+template <int DIR, typename T>
+struct Dft<1, DIR, T> {
+    __device__ __forceinline__ static void run(cpx<T>*) {}
+};
+
+template <int DIR, typename T>
+struct Dft<2, DIR, T> {
+    __device__ __forceinline__ static void run(cpx<T>* v)
+    {
+        cpx<T> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+
+template <int DIR, typename T>
+struct Dft<3, DIR, T> {
+    __device__ __forceinline__ static void run(cpx<T>* v)
+    {
+        const T s3 = (T)0.86602540378443864676;  // sin(2 pi / 3)
+        cpx<T> a = v[0], b = v[1], c = v[2];
+        cpx<T> t1 = cadd(b, c);
+        cpx<T> t2 = {a.x - (T)0.5 * t1.x, a.y - (T)0.5 * t1.y};
+        cpx<T> t3 = mul_i<DIR>(cscale(csub(b, c), s3));
+        v[0] = cadd(a, t1);
+        v[1] = cadd(t2, t3);
+        v[2] = csub(t2, t3);
+    }
+};
+
+template <int DIR, typename T>
+struct Dft<4, DIR, T> {
+    __device__ __forceinline__ static void run(cpx<T>* v)
+    {
+        cpx<T> a = v[0], b = v[1], c = v[2], d = v[3];
+        cpx<T> s0 = cadd(a, c), d0 = csub(a, c);
+        cpx<T> s1 = cadd(b, d), d1 = mul_i<DIR>(csub(b, d));
+        v[0] = cadd(s0, s1);
+        v[1] = cadd(d0, d1);
+        v[2] = csub(s0, s1);
+        v[3] = csub(d0, d1);
+    }
+};
+
+template <int DIR, typename T>
+struct Dft<5, DIR, T> {
+    __device__ __forceinline__ static void run(cpx<T>* v)
+    {
+        const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+        const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
+        cpx<T> a = v[0];
+        cpx<T> t1 = cadd(v[1], v[4]), t3 = csub(v[1], v[4]);
+        cpx<T> t2 = cadd(v[2], v[3]), t4 = csub(v[2], v[3]);
+        cpx<T> r1 = {a.x + c1 * t1.x + c2 * t2.x, a.y + c1 * t1.y + c2 * t2.y};
+        cpx<T> r2 = {a.x + c2 * t1.x + c1 * t2.x, a.y + c2 * t1.y + c1 * t2.y};
+        cpx<T> i1 = mul_i<DIR>(cpx<T>{s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y});
+        cpx<T> i2 = mul_i<DIR>(cpx<T>{s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y});
+        v[0] = cadd(a, cadd(t1, t2));
+        v[1] = cadd(r1, i1);
+        v[4] = csub(r1, i1);
+        v[2] = cadd(r2, i2);
+        v[3] = csub(r2, i2);
+    }
+};
+
+// R = A * B by one Cooley-Tukey split: input n = B n1 + n2, output
+// k = k1 + A k2; inner DFT_A over n1, twiddle w_R^{n2 k1}, outer DFT_B over n2.
+template <int A, int B, int DIR, typename T>
+struct DftSplit {
+    static constexpr int R = A * B;
+    template <int N2, int K1>
+    __device__ __forceinline__ static void rot(cpx<T> (&y)[B][A])
+    {
+        y[N2][K1] = rot_const<R, N2 * K1, DIR>(y[N2][K1]);
+        if constexpr (K1 + 1 < A) rot<N2, K1 + 1>(y);
+        else if constexpr (N2 + 1 < B) rot<N2 + 1, 0>(y);
+    }
+    __device__ __forceinline__ static void run(cpx<T>* v)
+    {
+        cpx<T> y[B][A];
+#pragma unroll
+        for (int n2 = 0; n2 < B; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < A; ++n1) y[n2][n1] = v[B * n1 + n2];
+            Dft<A, DIR, T>::run(y[n2]);
+        }
+        rot<1, 1>(y);
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) {
+            cpx<T> z[B];
+#pragma unroll
+            for (int n2 = 0; n2 < B; ++n2) z[n2] = y[n2][k1];
+            Dft<B, DIR, T>::run(z);
+#pragma unroll
+            for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = z[k2];
+        }
+    }
+};
+
+template <int DIR, typename T>
+struct Dft<8, DIR, T> {
+    __device__ __forceinline__ static void run(cpx<T>* v) { DftSplit<2, 4, DIR, T>::run(v); }
+};
+
+template <int DIR, typename T>
+struct Dft<16, DIR, T> {
+    __device__ __forceinline__ static void run(cpx<T>* v) { DftSplit<4, 4, DIR, T>::run(v); }
+};
+
+// ---------------------------------------------------------------- plans
+template <int... Rs>
+struct Radices;
+
+template <int R0, int... Rest>
+struct Radices<R0, Rest...> {
+    static constexpr int first = R0;
+    static constexpr int count = 1 + sizeof...(Rest);
+    static constexpr int product = R0 * Radices<Rest...>::product;
+    static constexpr int last = Radices<Rest...>::count == 0 ? R0 : Radices<Rest...>::last;
+};
+template <>
+struct Radices<> {
+    static constexpr int count = 0;
+    static constexpr int product = 1;
+    static constexpr int last = 1;
+};
+
+// LDS position of element pos of a line: one pad slot every PD elements
+// breaks the stride-R bank pattern of the first exchange.
+template <int PD>
+__device__ __forceinline__ int lds_pos(int pos) { return pos + pos / PD; }
+
+// Stage s of a transform of length N held by G threads: compute the
+// butterflies, then (unless it is the last stage) exchange through LDS into
+// the register layout of the next stage.  lds points at this line's slot 0;
+// element pos lives at lds[lds_pos<PD>(pos) * LS].
+template <int N, int G, int DIR, int PD, int LS, typename T, int P, int... Rs>
+struct Stages;
+
+template <int N, int G, int DIR, int PD, int LS, typename T, int P, int R, int... Rest>
+struct Stages<N, G, DIR, PD, LS, T, P, R, Rest...> {
+    static constexpr int E = N / G;
+    static constexpr int NB = N / (R * G);
+    static_assert(NB * R * G == N, "G must divide N / R for every radix");
+
+    __device__ __forceinline__ static void run(cpx<T> (&v)[E], int t, cpx<T>* lds, const cpx<T>* __restrict__ tw)
+    {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int b = t + q * G;
+            if constexpr (P > 1) {
+                const int k = b % P;
+#pragma unroll
+                for (int m = 1; m < R; ++m) v[q * R + m] = twiddle<DIR>(v[q * R + m], tw[m * k * (N / (P * R))]);
+            }
+            Dft<R, DIR, T>::run(&v[q * R]);
+        }
+        if constexpr (sizeof...(Rest) > 0) {
+            constexpr int R2 = Radices<Rest...>::first;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int b = t + q * G;
+                const int k = b % P;
+                const int j = (b - k) * R + k;
+#pragma unroll
+                for (int m = 0; m < R; ++m) lds[lds_pos<PD>(j + m * P) * LS] = v[q * R + m];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < N / (R2 * G); ++q)
+#pragma unroll
+                for (int m = 0; m < R2; ++m) v[q * R2 + m] = lds[lds_pos<PD>(t + q * G + m * (N / R2)) * LS];
+            __syncthreads();
+            Stages<N, G, DIR, PD, LS, T, P * R, Rest...>::run(v, t, lds, tw);
+        }
+    }
+};
+
+template <int N_, int G_, class Rad>
+struct Plan;
+
+template <int N_, int G_, int... Rs>
+struct Plan<N_, G_, Radices<Rs...>> {
+    static constexpr int N = N_, G = G_, E = N_ / G_;
+    using Rad = Radices<Rs...>;
+    static constexpr int R0 = Rad::first, RL = Rad::last;
+    static_assert(Rad::product == N_, "radices must multiply to N");
+    // LDS elements per line (with padding)
+    static constexpr int lds_len = N_ + N_ / R0 + 1;
+
+    template <int DIR, int LS, typename T>
+    __device__ __forceinline__ static void run(cpx<T> (&v)[E], int t, cpx<T>* lds, const cpx<T>* __restrict__ tw)
+    {
+        Stages<N_, G_, DIR, R0, LS, T, 1, Rs...>::run(v, t, lds, tw);
+    }
+    // position of register element i = q * R + m at stage-0 input / final output
+    __device__ __forceinline__ static constexpr int in_pos(int t, int i) { return t + (i / R0) * G + (i % R0) * (N / R0); }
+    __device__ __forceinline__ static constexpr int out_pos(int t, int i) { return t + (i / RL) * G + (i % RL) * (N / RL); }
+};
+
+}  // namespace ns

@@ -1,0 +1,202 @@
+// Size-independent kernels: conversion between the public half-spectrum
+// (R2C) layout and the compact retained-mode layout, the in-place
+// truncation + Leray projection (eq. (2.5)), and the energy spectrum
+// (the energy-spectrum writer of Sec. 2.4).
+#include "fft_engine.hpp"
+#include "misc_kernels.hpp"
+
+namespace ns {
+
+namespace {
+
+__device__ __forceinline__ int full_index(int j, int K, int M, int N) { return j <= K ? j : j - M + N; }
+
+// R2C [3][N][N][N/2+1] -> compact [3][M][M][Mx]
+template <typename R>
+__global__ void k_pack(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out, int N, int K)
+{
+    const int M = 2 * K + 1, Mx = K + 1, Nh = N / 2 + 1;
+    const long long total = 3LL * M * M * Mx;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    long long r = idx;
+    const int kx = (int)(r % Mx);
+    r /= Mx;
+    const int jy = (int)(r % M);
+    r /= M;
+    const int jz = (int)(r % M);
+    const int c = (int)(r / M);
+    const int nz = full_index(jz, K, M, N), ny = full_index(jy, K, M, N);
+    out[idx] = in[(((long long)c * N + nz) * N + ny) * Nh + kx];
+}
+
+// compact -> R2C, zero outside the retained cube
+template <typename R>
+__global__ void k_unpack(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out, int N, int K)
+{
+    const int M = 2 * K + 1, Mx = K + 1, Nh = N / 2 + 1;
+    const long long total = 3LL * N * N * Nh;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    long long r = idx;
+    const int kx = (int)(r % Nh);
+    r /= Nh;
+    const int ny = (int)(r % N);
+    r /= N;
+    const int nz = (int)(r % N);
+    const int c = (int)(r / N);
+    const int jy = ny <= K ? ny : (ny >= N - K ? ny - N + M : -1);
+    const int jz = nz <= K ? nz : (nz >= N - K ? nz - N + M : -1);
+    cpx<R> v = {0, 0};
+    if (kx <= K && jy >= 0 && jz >= 0) v = in[(((long long)c * M + jz) * M + jy) * Mx + kx];
+    out[idx] = v;
+}
+
+// in place on R2C: zero outside the cube, Leray projection inside
+template <typename R>
+__global__ void k_project(cpx<R>* u, int N, int K)
+{
+    const int Nh = N / 2 + 1;
+    const long long plane = (long long)N * N * Nh;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= plane) return;
+    const int kxi = (int)(idx % Nh);
+    const int ny = (int)((idx / Nh) % N);
+    const int nz = (int)(idx / ((long long)Nh * N));
+    const int kyi = ny < N / 2 ? ny : ny - N, kzi = nz < N / 2 ? nz : nz - N;
+    cpx<R> v0 = u[idx], v1 = u[plane + idx], v2 = u[2 * plane + idx];
+    if (kxi > K || kyi > K || -kyi > K || kzi > K || -kzi > K) {
+        v0 = v1 = v2 = {0, 0};
+    } else {
+        const int k2 = kxi * kxi + kyi * kyi + kzi * kzi;
+        if (k2 > 0) {
+            const R kx = (R)kxi, ky = (R)kyi, kz = (R)kzi, inv = (R)1 / (R)k2;
+            const R bx = (kx * v0.x + ky * v1.x + kz * v2.x) * inv;
+            const R by = (kx * v0.y + ky * v1.y + kz * v2.y) * inv;
+            v0.x -= kx * bx;
+            v0.y -= kx * by;
+            v1.x -= ky * bx;
+            v1.y -= ky * by;
+            v2.x -= kz * bx;
+            v2.y -= kz * by;
+        }
+    }
+    u[idx] = v0;
+    u[plane + idx] = v1;
+    u[2 * plane + idx] = v2;
+}
+
+__device__ __forceinline__ long long isqrt_ll(long long v)
+{
+    if (v <= 0) return 0;
+    long long r = (long long)sqrt((double)v);
+    while (r * r > v) --r;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return r;
+}
+
+// One block per shell kappa: E[kappa] = 1/2 sum |u_k|^2 over retained modes
+// with kappa^2 - kappa < |k|^2 <= kappa^2 + kappa (i.e. round(|k|) = kappa;
+// shell 0 is |k| = 0 alone),
+// weight 2 for k_x > 0 (the mirrored half).  Each thread walks a fixed set
+// of (k_z, k_y) rows in order and the block reduces in a fixed tree, so the
+// result is bitwise reproducible.
+constexpr int SPEC_THREADS = 256;
+
+template <typename R>
+__global__ void __launch_bounds__(SPEC_THREADS) k_spectrum(const cpx<R>* __restrict__ u, double* E, int N, int K,
+                                                           int kbins)
+{
+    __shared__ double red[SPEC_THREADS];
+    const int kappa = blockIdx.x;
+    const int Nh = N / 2 + 1, M = 2 * K + 1;
+    const long long plane = (long long)N * N * Nh;
+    // |k|^2 > kappa^2 - kappa, except that shell 0 starts at |k| = 0
+    const long long lo2 = kappa == 0 ? -1 : (long long)kappa * kappa - kappa;
+    const long long hi2 = (long long)kappa * kappa + kappa;
+    double acc = 0.0;
+    for (int r = threadIdx.x; r < M * M; r += SPEC_THREADS) {
+        const int jz = r / M, jy = r % M;
+        const int kz = jz <= K ? jz : jz - M, ky = jy <= K ? jy : jy - M;
+        const long long q = (long long)kz * kz + (long long)ky * ky;
+        const long long B = hi2 - q;
+        if (B < 0) continue;
+        const long long A = lo2 - q;
+        const int lo = A < 0 ? 0 : (int)isqrt_ll(A) + 1;
+        int hi = (int)isqrt_ll(B);
+        if (hi > K) hi = K;
+        const int nz = kz < 0 ? kz + N : kz, ny = ky < 0 ? ky + N : ky;
+        const long long base = ((long long)nz * N + ny) * Nh;
+        for (int kx = lo; kx <= hi; ++kx) {
+            double e = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                const cpx<R> v = u[c * plane + base + kx];
+                e += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+            }
+            acc += (kx == 0 ? 0.5 : 1.0) * e;
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = SPEC_THREADS / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && kappa < kbins) E[kappa] = red[0];
+}
+
+__global__ void k_fill(double* p, double v, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+inline unsigned nblocks(long long total, int threads) { return (unsigned)((total + threads - 1) / threads); }
+
+}  // namespace
+
+hipError_t launch_pack(bool f64, const void* in, void* out, int N, int K, hipStream_t s)
+{
+    const int M = 2 * K + 1;
+    const long long total = 3LL * M * M * (K + 1);
+    if (f64) hipLaunchKernelGGL(k_pack<double>, dim3(nblocks(total, 256)), dim3(256), 0, s, (const cpx<double>*)in, (cpx<double>*)out, N, K);
+    else hipLaunchKernelGGL(k_pack<float>, dim3(nblocks(total, 256)), dim3(256), 0, s, (const cpx<float>*)in, (cpx<float>*)out, N, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(bool f64, const void* in, void* out, int N, int K, hipStream_t s)
+{
+    const long long total = 3LL * N * N * (N / 2 + 1);
+    if (f64) hipLaunchKernelGGL(k_unpack<double>, dim3(nblocks(total, 256)), dim3(256), 0, s, (const cpx<double>*)in, (cpx<double>*)out, N, K);
+    else hipLaunchKernelGGL(k_unpack<float>, dim3(nblocks(total, 256)), dim3(256), 0, s, (const cpx<float>*)in, (cpx<float>*)out, N, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_project(bool f64, void* u, int N, int K, hipStream_t s)
+{
+    const long long total = (long long)N * N * (N / 2 + 1);
+    if (f64) hipLaunchKernelGGL(k_project<double>, dim3(nblocks(total, 256)), dim3(256), 0, s, (cpx<double>*)u, N, K);
+    else hipLaunchKernelGGL(k_project<float>, dim3(nblocks(total, 256)), dim3(256), 0, s, (cpx<float>*)u, N, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_spectrum(bool f64, const void* u, double* E, int N, int K, int kbins, hipStream_t s)
+{
+    if (kbins <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(nblocks(kbins, 256)), dim3(256), 0, s, E, 0.0, kbins);
+    // shells beyond round(sqrt(3) K) are empty
+    int kmax = (int)ceil(sqrt(3.0) * K) + 1;
+    int nb = kbins < kmax ? kbins : kmax;
+    if (f64) hipLaunchKernelGGL(k_spectrum<double>, dim3(nb), dim3(SPEC_THREADS), 0, s, (const cpx<double>*)u, E, N, K, kbins);
+    else hipLaunchKernelGGL(k_spectrum<float>, dim3(nb), dim3(SPEC_THREADS), 0, s, (const cpx<float>*)u, E, N, K, kbins);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, double v, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(nblocks(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace ns

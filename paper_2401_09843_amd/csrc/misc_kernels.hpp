@@ -1,0 +1,11 @@
+// Launchers of the size-independent kernels (misc_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ns {
+hipError_t launch_pack(bool f64, const void* r2c, void* compact, int N, int K, hipStream_t s);
+hipError_t launch_unpack(bool f64, const void* compact, void* r2c, int N, int K, hipStream_t s);
+hipError_t launch_project(bool f64, void* r2c, int N, int K, hipStream_t s);
+hipError_t launch_spectrum(bool f64, const void* r2c, double* E, int N, int K, int kbins, hipStream_t s);
+hipError_t launch_fill(double* p, double v, int n, hipStream_t s);
+}  // namespace ns

@@ -1,0 +1,392 @@
+// Pass kernels of one right-hand-side evaluation (Algorithm 2 with the
+// padded inverse / unpadding forward transforms of Algorithm 3 replaced by
+// pruned passes on the N^3 grid: zero rows are never stored).
+//
+//   I1  inverse C2C along z, compact k_z rows M -> N    (k_colfft, COL_INV_PAD)
+//   I2  inverse C2C along y, compact k_y rows M -> N    (k_colfft, COL_INV_PAD)
+//   X   C2R along x, six products u_i u_j, R2C along x  (k_xline, X_RHS)
+//   F2  forward C2C along y, keep the M retained rows   (k_colfft, COL_FWD_TRUNC)
+//   F3  forward C2C along z of the six products, then -i k.B-hat, the Leray
+//       projection (eq. (2.5)), hyperviscosity (eqs. (2.1)-(2.3)) and the
+//       SSP-RK3 stage combination (eq. (2.6))            (k_f3, F3_RHS)
+//
+// Strided axes are transformed by tiles of T neighbouring columns: each
+// thread loads whole rows of T columns (coalesced) straight into registers,
+// and only the Stockham exchanges go through LDS.
+#pragma once
+#include "args.hpp"
+#include "fft_engine.hpp"
+
+namespace ns {
+
+enum { COL_INV_PAD = 0, COL_FWD_TRUNC = 1 };
+enum { X_RHS = 0, X_FWD3 = 1, X_INV3 = 2 };
+enum { F3_RHS = 0, F3_PROJ = 1 };
+
+// compact index of FFT row n (wavenumber n or n - N), or -1 outside |k| <= K
+__device__ __forceinline__ int compact_of(int n, int N, int K, int M)
+{
+    return n <= K ? n : (n >= N - K ? n - N + M : -1);
+}
+
+// ------------------------------------------------------------------ I1/I2/F2
+template <class P, int T, int DIR, int MODE, typename R>
+__global__ void __launch_bounds__(P::G* T) k_colfft(ColArgs a)
+{
+    constexpr int N = P::N, E = P::E;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
+    const int tid = threadIdx.x, c = tid % T, g = tid / T;
+    const long long q = (long long)blockIdx.x * T + c;
+    const bool valid = q < a.Q;
+    const long long outer = valid ? q / a.S : 0;
+    const long long inner = valid ? q % a.S : 0;
+    const cpx<R>* __restrict__ in = static_cast<const cpx<R>*>(a.in) + outer * a.in_os + inner;
+    cpx<R>* __restrict__ out = static_cast<cpx<R>*>(a.out) + outer * a.out_os + inner;
+    const cpx<R>* __restrict__ tw = static_cast<const cpx<R>*>(a.tw);
+
+    cpx<R> v[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int n = P::in_pos(g, i);
+        int r = n;
+        if constexpr (MODE == COL_INV_PAD) r = compact_of(n, N, a.K, a.M);
+        v[i] = (valid && r >= 0) ? in[r * a.S] : cpx<R>{0, 0};
+    }
+    P::template run<DIR, T>(v, g, lds + c, tw);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int n = P::out_pos(g, i);
+        if constexpr (MODE == COL_INV_PAD) {
+            if (valid) out[n * a.S] = v[i];
+        } else {
+            const int r = compact_of(n, N, a.K, a.M);
+            if (valid && r >= 0) out[r * a.S] = cscale(v[i], (R)a.scale);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ X pass
+// Two real lines l1 = 2u, l2 = 2u+1 share one complex transform: for a C2R,
+// Z = A + iB with A, B the Hermitian half spectra gives z = a + i b; for an
+// R2C, Z = FFT(a + i b) splits as A_k = (Z_k + conj Z_{N-k})/2,
+// B_k = (Z_k - conj Z_{N-k})/(2i).
+template <class PI, class PF, int U, int MODE, typename R>
+__global__ void __launch_bounds__(PI::G* U) k_xline(XArgs a)
+{
+    constexpr int N = PI::N, G = PI::G, E = PI::E;
+    static_assert(PF::G == G && PF::N == N, "plans must match");
+    static_assert(PF::R0 == PI::RL, "forward plan must start with the inverse plan's last radix");
+    constexpr int LL = PI::lds_len > PF::lds_len ? PI::lds_len : PF::lds_len;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int tid = threadIdx.x, u = tid / G, t = tid % G;
+    cpx<R>* my = reinterpret_cast<cpx<R>*>(smem_raw) + u * LL;
+    const long long unit = (long long)blockIdx.x * U + u;
+    const bool valid = unit < a.nunits;
+    const long long L = valid ? 2 * unit : 0;
+    const long long samp = L / ((long long)N * N);
+    const long long l1 = L % ((long long)N * N);
+    const int K = a.K, Mx = K + 1;
+    const cpx<R>* __restrict__ tw = static_cast<const cpx<R>*>(a.tw);
+
+    // inverse (C2R) of component c of both lines into z = a + i b
+    auto load_inv = [&](int c, cpx<R>(&v)[E]) {
+        const cpx<R>* p1 = static_cast<const cpx<R>*>(a.in) + samp * a.in_ss + c * a.in_cs + l1 * Mx;
+        const cpx<R>* p2 = p1 + Mx;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int n = PI::in_pos(t, i);
+            cpx<R> A = {0, 0}, B = {0, 0};
+            if (valid) {
+                if (n <= K) {
+                    A = p1[n];
+                    B = p2[n];
+                    if (n == 0) A.y = B.y = 0;
+                } else if (n >= N - K) {
+                    const cpx<R> a1 = p1[N - n], b1 = p2[N - n];
+                    A = {a1.x, -a1.y};
+                    B = {b1.x, -b1.y};
+                }
+            }
+            v[i] = {A.x - B.y, A.y + B.x};
+        }
+        PI::template run<+1, 1>(v, t, my, tw);
+    };
+
+    // forward (R2C) of v = a + i b; store k_x <= K of both lines as product p
+    auto fwd_store = [&](int p, cpx<R>(&v)[E]) {
+        PF::template run<-1, 1>(v, t, my, tw);
+#pragma unroll
+        for (int i = 0; i < E; ++i) my[lds_pos<PF::R0>(PF::out_pos(t, i))] = v[i];
+        __syncthreads();
+        const R h = (R)(0.5 * a.scale);
+        cpx<R>* o1 = static_cast<cpx<R>*>(a.out) + samp * a.out_ss + p * a.out_cs + l1 * Mx;
+        cpx<R>* o2 = o1 + Mx;
+        for (int kx = t; kx <= K; kx += G) {
+            const cpx<R> zk = my[lds_pos<PF::R0>(kx)];
+            const cpx<R> zm = my[lds_pos<PF::R0>((N - kx) % N)];
+            if (valid) {
+                o1[kx] = {(zk.x + zm.x) * h, (zk.y - zm.y) * h};
+                o2[kx] = {(zk.y + zm.y) * h, (zm.x - zk.x) * h};
+            }
+        }
+        __syncthreads();
+    };
+
+    if constexpr (MODE == X_RHS) {
+        cpx<R> z0[E], z1[E], z2[E], v[E];
+        load_inv(0, z0);
+        load_inv(1, z1);
+        load_inv(2, z2);
+        // B_ij = u_i u_j, upper triangle (xx, xy, xz, yy, yz, zz); real parts
+        // belong to line l1, imaginary parts to line l2
+#pragma unroll 1
+        for (int p = 0; p < 6; ++p) {
+            auto mul = [&](const cpx<R>(&za)[E], const cpx<R>(&zb)[E]) {
+#pragma unroll
+                for (int i = 0; i < E; ++i) v[i] = {za[i].x * zb[i].x, za[i].y * zb[i].y};
+            };
+            switch (p) {
+                case 0: mul(z0, z0); break;
+                case 1: mul(z0, z1); break;
+                case 2: mul(z0, z2); break;
+                case 3: mul(z1, z1); break;
+                case 4: mul(z1, z2); break;
+                default: mul(z2, z2); break;
+            }
+            fwd_store(p, v);
+        }
+    } else if constexpr (MODE == X_INV3) {
+        cpx<R> v[E];
+        for (int c = 0; c < 3; ++c) {
+            load_inv(c, v);
+            R* o1 = static_cast<R*>(a.out) + samp * a.out_ss + c * a.out_cs + l1 * N;
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const int x = PI::out_pos(t, i);
+                if (valid) {
+                    o1[x] = v[i].x;
+                    o1[N + x] = v[i].y;
+                }
+            }
+        }
+    } else {  // X_FWD3
+        cpx<R> v[E];
+        for (int c = 0; c < 3; ++c) {
+            const R* p1 = static_cast<const R*>(a.in) + samp * a.in_ss + c * a.in_cs + l1 * N;
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const int x = PF::in_pos(t, i);
+                v[i] = valid ? cpx<R>{p1[x], p1[N + x]} : cpx<R>{0, 0};
+            }
+            fwd_store(c, v);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ F3 pass
+template <class P, int T, int MODE, typename R>
+__global__ void __launch_bounds__(P::G* T) k_f3(F3Args a)
+{
+    constexpr int N = P::N, E = P::E;
+    constexpr int NC = MODE == F3_RHS ? 6 : 3;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
+    const int tid = threadIdx.x, c = tid % T, g = tid / T;
+    const long long q = (long long)blockIdx.x * T + c;
+    const bool valid = q < a.Q;
+    const long long samp = valid ? q / a.MMx : 0;
+    const int s = valid ? (int)(q % a.MMx) : 0;
+    const int K = a.K, M = a.M, Mx = a.Mx;
+    const int jy = s / Mx, kxi = s % Mx;
+    const int kyi = jy <= K ? jy : jy - M;
+    const R kx = (R)kxi, ky = (R)kyi;
+    const cpx<R>* __restrict__ in = static_cast<const cpx<R>*>(a.in) + samp * a.in_ss + s;
+    const cpx<R>* __restrict__ tw = static_cast<const cpx<R>*>(a.tw);
+
+    cpx<R> acc[3][E];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int i = 0; i < E; ++i) acc[j][i] = {0, 0};
+
+#pragma unroll 1
+    for (int p = 0; p < NC; ++p) {
+        cpx<R> v[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int n = P::in_pos(g, i);
+            v[i] = valid ? in[p * a.in_cs + (long long)n * a.MMx] : cpx<R>{0, 0};
+        }
+        P::template run<-1, T>(v, g, lds + c, tw);
+        if constexpr (MODE == F3_RHS) {
+            // component p = (i, j) of the upper triangle adds k_j B to b_i
+            // and, off the diagonal, k_i B to b_j: b_r += (wxy_r + wz_r k_z) B
+            R w[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // [r][axis]
+            switch (p) {
+                case 0: w[0][0] = 1; break;
+                case 1: w[0][1] = 1; w[1][0] = 1; break;
+                case 2: w[0][2] = 1; w[2][0] = 1; break;
+                case 3: w[1][1] = 1; break;
+                case 4: w[1][2] = 1; w[2][1] = 1; break;
+                default: w[2][2] = 1; break;
+            }
+            const R wxy0 = w[0][0] * kx + w[0][1] * ky, wz0 = w[0][2];
+            const R wxy1 = w[1][0] * kx + w[1][1] * ky, wz1 = w[1][2];
+            const R wxy2 = w[2][0] * kx + w[2][1] * ky, wz2 = w[2][2];
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const int n = P::out_pos(g, i);
+                const R kz = (R)(n < N / 2 ? n : n - N);
+                const R c0 = wxy0 + wz0 * kz, c1 = wxy1 + wz1 * kz, c2 = wxy2 + wz2 * kz;
+                acc[0][i].x += c0 * v[i].x;
+                acc[0][i].y += c0 * v[i].y;
+                acc[1][i].x += c1 * v[i].x;
+                acc[1][i].y += c1 * v[i].y;
+                acc[2][i].x += c2 * v[i].x;
+                acc[2][i].y += c2 * v[i].y;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                acc[0][i] = p == 0 ? v[i] : acc[0][i];
+                acc[1][i] = p == 1 ? v[i] : acc[1][i];
+                acc[2][i] = p == 2 ? v[i] : acc[2][i];
+            }
+        }
+    }
+
+    const R sc = (R)a.scale;
+    const double dts = (MODE == F3_RHS && valid) ? a.dt[samp] : 0.0;
+    const R* __restrict__ rate = static_cast<const R*>(a.rate);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int n = P::out_pos(g, i);
+        const int jz = compact_of(n, N, K, M);
+        if (!valid || jz < 0) continue;
+        const int kzi = n <= K ? n : n - N;
+        const R kz = (R)kzi;
+        cpx<R> b[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            if constexpr (MODE == F3_RHS) b[j] = {acc[j][i].y * sc, -acc[j][i].x * sc};  // -i * sum
+            else b[j] = {acc[j][i].x * sc, acc[j][i].y * sc};
+        }
+        const int k2 = kxi * kxi + kyi * kyi + kzi * kzi;
+        if (k2 > 0) {
+            const R inv = (R)1 / (R)k2;
+            const cpx<R> kb = {kx * b[0].x + ky * b[1].x + kz * b[2].x, kx * b[0].y + ky * b[1].y + kz * b[2].y};
+            const R kv[3] = {kx, ky, kz};
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                b[j].x -= kv[j] * kb.x * inv;
+                b[j].y -= kv[j] * kb.y * inv;
+            }
+        }
+        const long long st = samp * a.st_ss + (long long)jz * a.MMx + s;
+        if constexpr (MODE == F3_RHS) {
+            const R rt = rate[k2];
+            const R ca = (R)a.ca, cb = (R)a.cb, cdt = (R)(a.cc * dts);
+            const cpx<R>* us = static_cast<const cpx<R>*>(a.us) + st;
+            const cpx<R>* u0 = static_cast<const cpx<R>*>(a.u0) + st;
+            cpx<R>* o = static_cast<cpx<R>*>(a.out) + st;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const cpx<R> w = us[j * a.st_cs];
+                cpx<R> f = {b[j].x - rt * w.x, b[j].y - rt * w.y};
+                cpx<R> r = {cb * w.x + cdt * f.x, cb * w.y + cdt * f.y};
+                if (a.ca != 0.0) {
+                    const cpx<R> w0 = u0[j * a.st_cs];
+                    r.x += ca * w0.x;
+                    r.y += ca * w0.y;
+                }
+                o[j * a.st_cs] = r;
+            }
+        } else {
+            cpx<R>* o = static_cast<cpx<R>*>(a.out) + st;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) o[j * a.st_cs] = b[j];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launch
+template <typename Args>
+inline hipError_t launch_k(void (*k)(Args), long long blocks, int threads, size_t lds, hipStream_t s, const Args& a,
+                           bool& attr_done)
+{
+    if (blocks <= 0) return hipSuccess;
+    if (lds > 65536 && !attr_done) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+        attr_done = true;
+    }
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+// Per-size schedule: each pass has its own line plan (threads per line and
+// radix order): the column passes (G, Rad), the x pass (GX, XRad and its
+// reverse XRadRev for the forward half) and the fused z pass (GF, FRad);
+// T / TF columns per block for the column and fused z passes and U line
+// pairs per block for the x pass, for FP32 and FP64.
+template <int N>
+struct SizeCfg;
+
+template <int N, typename R>
+struct Launch {
+    using C = SizeCfg<N>;
+    using P = Plan<N, C::G, typename C::Rad>;
+    using PX = Plan<N, C::GX, typename C::XRad>;
+    using PXR = Plan<N, C::GX, typename C::XRadRev>;
+    using PF = Plan<N, C::GF, typename C::FRad>;
+    static constexpr bool f64 = sizeof(R) == 8;
+    static constexpr int T = f64 ? C::T64 : C::T32;
+    static constexpr int TF = f64 ? C::TF64 : C::TF32;
+    static constexpr int U = f64 ? C::U64 : C::U32;
+    static constexpr int XL = PX::lds_len > PXR::lds_len ? PX::lds_len : PXR::lds_len;
+
+    static hipError_t col_inv(const ColArgs& a, hipStream_t s)
+    {
+        static bool done = false;
+        return launch_k(k_colfft<P, T, +1, COL_INV_PAD, R>, (a.Q + T - 1) / T, C::G * T,
+                        sizeof(cpx<R>) * P::lds_len * T, s, a, done);
+    }
+    static hipError_t col_fwd(const ColArgs& a, hipStream_t s)
+    {
+        static bool done = false;
+        return launch_k(k_colfft<P, T, -1, COL_FWD_TRUNC, R>, (a.Q + T - 1) / T, C::G * T,
+                        sizeof(cpx<R>) * P::lds_len * T, s, a, done);
+    }
+    template <int MODE>
+    static hipError_t xl(const XArgs& a, hipStream_t s)
+    {
+        static bool done = false;
+        return launch_k(k_xline<PX, PXR, U, MODE, R>, (a.nunits + U - 1) / U, C::GX * U, sizeof(cpx<R>) * XL * U, s,
+                        a, done);
+    }
+    template <int MODE>
+    static hipError_t f3(const F3Args& a, hipStream_t s)
+    {
+        static bool done = false;
+        return launch_k(k_f3<PF, TF, MODE, R>, (a.Q + TF - 1) / TF, C::GF * TF, sizeof(cpx<R>) * PF::lds_len * TF, s,
+                        a, done);
+    }
+    static SizeKernels make()
+    {
+        SizeKernels k;
+        k.N = N;
+        k.col_inv = col_inv;
+        k.col_fwd = col_fwd;
+        k.x_rhs = xl<X_RHS>;
+        k.x_fwd3 = xl<X_FWD3>;
+        k.x_inv3 = xl<X_INV3>;
+        k.f3_rhs = f3<F3_RHS>;
+        k.f3_proj = f3<F3_PROJ>;
+        k.desc = C::desc;
+        return k;
+    }
+};
+
+}  // namespace ns

@@ -1,0 +1,11 @@
+// Kernels for grid size N = 12 (FP32 and FP64).
+#include "sizes.hpp"
+
+namespace ns {
+const SizeKernels* kernels_12(bool f64)
+{
+    static const SizeKernels k32 = Launch<12, float>::make();
+    static const SizeKernels k64 = Launch<12, double>::make();
+    return f64 ? &k64 : &k32;
+}
+}  // namespace ns

@@ -1,0 +1,11 @@
+// Kernels for grid size N = 16 (FP32 and FP64).
+#include "sizes.hpp"
+
+namespace ns {
+const SizeKernels* kernels_16(bool f64)
+{
+    static const SizeKernels k32 = Launch<16, float>::make();
+    static const SizeKernels k64 = Launch<16, double>::make();
+    return f64 ? &k64 : &k32;
+}
+}  // namespace ns

@@ -1,0 +1,11 @@
+// Kernels for grid size N = 48 (FP32 and FP64).
+#include "sizes.hpp"
+
+namespace ns {
+const SizeKernels* kernels_48(bool f64)
+{
+    static const SizeKernels k32 = Launch<48, float>::make();
+    static const SizeKernels k64 = Launch<48, double>::make();
+    return f64 ? &k64 : &k32;
+}
+}  // namespace ns

@@ -136,3 +136,31 @@ def half_spectrum(u: np.ndarray) -> np.ndarray:
     """numpy's normalised half spectrum of a real field (the solver's public
     layout): rfftn(u, norm="forward") over the last three axes."""
     return np.fft.rfftn(u, axes=(-3, -2, -1), norm="forward")
+
+
+def shear_layer_torch(n: int, seed: int = 0, rho: float = 0.05, delta=0.025, nmodes: int = 16, kmax: float = 4.0,
+                      device="cuda", dtype=None):
+    """The field of shear_layer(n, seed, ...) tabulated with torch on a
+    device (same random draws, same formula), for grids too large for the
+    host.  Returns (u, delta, modes) with u a torch tensor [3, n, n, n]."""
+    import torch
+
+    dtype = dtype or torch.float64
+    rng = np.random.default_rng(seed)
+    if isinstance(delta, (tuple, list)):
+        delta = float(rng.uniform(delta[0], delta[1]))
+    modes = draw_modes(rng, nmodes, kmax)
+    x1 = 2.0 * np.pi * torch.arange(n, device=device, dtype=torch.float64) / n
+    X = x1.view(1, 1, n)
+    Y = x1.view(1, n, 1)
+    Z = x1.view(n, 1, 1)
+    u = torch.zeros((3, n, n, n), device=device, dtype=dtype)
+    prof = torch.where(x1 < np.pi, torch.tanh((x1 - np.pi / 2) / rho), torch.tanh((1.5 * np.pi - x1) / rho))
+    u[0] += prof.view(1, n, 1).to(dtype)
+    for k, a, phi in modes:
+        c = torch.cos(float(k[0]) * X + float(k[1]) * Y + float(k[2]) * Z + float(phi)).to(dtype)
+        for comp in range(3):
+            if a[comp] != 0.0:
+                u[comp].add_(c, alpha=float(delta * a[comp]))
+        del c
+    return u, float(delta), modes

@@ -1,0 +1,225 @@
+"""Thin ctypes binding of libns.so (include/ns.h).
+
+Only argument marshalling happens here: tensors are passed as device
+pointers and every step of the computation runs in the library's HIP
+kernels.  PyTorch supplies device memory and the stream.  There is no CPU
+fallback: if the library or a GPU is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libns.so")
+
+NS_OK, NS_ERR_ARG, NS_ERR_UNSUPPORTED, NS_ERR_OOM, NS_ERR_HIP, NS_ERR_STATE, NS_ERR_NONFINITE = range(7)
+NS_F32, NS_F64 = 0, 1
+NS_USE_GRAPH, NS_CHECK_FINITE, NS_NO_TUNE = 1, 2, 4
+
+# every symbol the header declares
+EXPORTS = ("ns_init", "ns_destroy", "ns_last_error", "ns_workspace_bytes", "ns_supported_sizes", "ns_forward",
+           "ns_inverse", "ns_project", "ns_rhs", "ns_step", "ns_tape_bytes", "ns_step_taped", "ns_adjoint_step",
+           "ns_energy_spectrum", "ns_sync", "ns_profile", "ns_profile_read")
+NS_NPASS = 5
+PASS_NAMES = ("I1_inv_z", "I2_inv_y", "X_c2r_prod_r2c", "F2_fwd_y", "F3_fwd_z_epilogue")
+
+
+class NSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("ns status %d: %s" % (status, msg))
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("nsamples", ctypes.c_int32), ("n", ctypes.POINTER(ctypes.c_int32)),
+                ("eps", ctypes.c_double), ("s", ctypes.c_double), ("m_cut", ctypes.c_double),
+                ("q_kind", ctypes.c_int32), ("theta", ctypes.c_double), ("flags", ctypes.c_uint32),
+                ("tune_cache", ctypes.c_char_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libns.so (built by __graft_entry__.build / _build.py)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libns.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, D, S = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+        PP = ctypes.POINTER(ctypes.c_void_p)
+        PD = ctypes.POINTER(ctypes.c_double)
+        sig = {
+            "ns_init": [ctypes.POINTER(_Params), P, ctypes.POINTER(P)],
+            "ns_destroy": [P],
+            "ns_workspace_bytes": [P, ctypes.POINTER(S)],
+            "ns_supported_sizes": [ctypes.POINTER(I32), I32, ctypes.POINTER(I32)],
+            "ns_forward": [P, PP, PP],
+            "ns_inverse": [P, PP, PP],
+            "ns_project": [P, PP],
+            "ns_rhs": [P, PP, PP],
+            "ns_step": [P, PP, PD, I32],
+            "ns_tape_bytes": [P, I32, ctypes.POINTER(S)],
+            "ns_step_taped": [P, PP, PD, I32, PP],
+            "ns_adjoint_step": [P, PP, PP, PD, PP],
+            "ns_energy_spectrum": [P, PP, P, I32],
+            "ns_sync": [P],
+            "ns_profile": [P, I32],
+            "ns_profile_read": [P, PD, ctypes.POINTER(ctypes.c_int64)],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.ns_last_error.argtypes = [P]
+        L.ns_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def supported_sizes() -> list:
+    L = lib()
+    buf = (ctypes.c_int32 * 64)()
+    cnt = ctypes.c_int32()
+    L.ns_supported_sizes(buf, 64, ctypes.byref(cnt))
+    return list(buf[: cnt.value])
+
+
+def _ptrs(ts: Sequence[torch.Tensor]):
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+class Solver:
+    """A context for one sample (n = int) or an ensemble (n = list of ints).
+
+    Spectra are complex tensors [3, N, N, N//2+1] (torch.fft.rfftn layout,
+    norm="forward"); physical fields are real tensors [3, N, N, N].  Methods
+    taking `uhat` accept a tensor (single sample) or a list of tensors."""
+
+    def __init__(self, n, dtype=torch.float32, eps=-1.0, s=1.5, m_cut=-1.0, q_kind=0, theta=1.0,
+                 graph=True, check_finite=False, tune=False, stream=None, device=None):
+        self.sizes = [int(n)] if isinstance(n, int) else [int(v) for v in n]
+        if dtype not in (torch.float32, torch.float64):
+            raise ValueError("dtype must be torch.float32 or torch.float64")
+        self.dtype = dtype
+        self.cdtype = torch.complex64 if dtype == torch.float32 else torch.complex128
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._L = lib()
+        nn = (ctypes.c_int32 * len(self.sizes))(*self.sizes)
+        flags = (NS_USE_GRAPH if graph else 0) | (NS_CHECK_FINITE if check_finite else 0) | (0 if tune else NS_NO_TUNE)
+        self._prm = _Params(NS_F32 if dtype == torch.float32 else NS_F64, len(self.sizes), nn, eps, s, m_cut,
+                            q_kind, theta, flags, None)
+        self._nn = nn
+        ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = self._L.ns_init(ctypes.byref(self._prm), ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(ctx))
+        if st != NS_OK:
+            raise NSError(st, self._L.ns_last_error(None).decode())
+        self._ctx = ctx
+
+    # ------------------------------------------------------------ helpers
+    def _check(self, st):
+        if st != NS_OK:
+            raise NSError(st, self._L.ns_last_error(self._ctx).decode())
+
+    def _list(self, x):
+        xs = [x] if isinstance(x, torch.Tensor) else list(x)
+        if len(xs) != len(self.sizes):
+            raise ValueError("expected %d tensors, got %d" % (len(self.sizes), len(xs)))
+        return xs
+
+    def _spec(self, xs):
+        for t, n in zip(xs, self.sizes):
+            if t.dtype != self.cdtype or t.device != self.device or not t.is_contiguous() \
+                    or tuple(t.shape) != (3, n, n, n // 2 + 1):
+                raise ValueError("spectrum must be a contiguous %s tensor [3,%d,%d,%d] on %s"
+                                 % (self.cdtype, n, n, n // 2 + 1, self.device))
+        return xs
+
+    def _phys(self, xs):
+        for t, n in zip(xs, self.sizes):
+            if t.dtype != self.dtype or t.device != self.device or not t.is_contiguous() or tuple(t.shape) != (3, n, n, n):
+                raise ValueError("field must be a contiguous %s tensor [3,%d,%d,%d] on %s"
+                                 % (self.dtype, n, n, n, self.device))
+        return xs
+
+    def _ret(self, x, outs):
+        return outs[0] if isinstance(x, torch.Tensor) else outs
+
+    def empty_spectrum(self):
+        return [torch.empty((3, n, n, n // 2 + 1), dtype=self.cdtype, device=self.device) for n in self.sizes]
+
+    # ------------------------------------------------------------ API
+    def forward(self, u):
+        xs = self._phys(self._list(u))
+        outs = self.empty_spectrum()
+        self._check(self._L.ns_forward(self._ctx, _ptrs(xs), _ptrs(outs)))
+        return self._ret(u, outs)
+
+    def inverse(self, uhat):
+        xs = self._spec(self._list(uhat))
+        outs = [torch.empty((3, n, n, n), dtype=self.dtype, device=self.device) for n in self.sizes]
+        self._check(self._L.ns_inverse(self._ctx, _ptrs(xs), _ptrs(outs)))
+        return self._ret(uhat, outs)
+
+    def project(self, uhat):
+        xs = self._spec(self._list(uhat))
+        self._check(self._L.ns_project(self._ctx, _ptrs(xs)))
+        return uhat
+
+    def rhs(self, uhat):
+        xs = self._spec(self._list(uhat))
+        outs = self.empty_spectrum()
+        self._check(self._L.ns_rhs(self._ctx, _ptrs(xs), _ptrs(outs)))
+        return self._ret(uhat, outs)
+
+    def step(self, uhat, dt, nsteps: int = 1):
+        xs = self._spec(self._list(uhat))
+        dts = [float(dt)] * len(xs) if not isinstance(dt, (list, tuple)) else [float(v) for v in dt]
+        arr = (ctypes.c_double * len(dts))(*dts)
+        self._check(self._L.ns_step(self._ctx, _ptrs(xs), arr, int(nsteps)))
+        return uhat
+
+    def spectrum(self, uhat, kbins: int):
+        xs = self._spec(self._list(uhat))
+        E = torch.zeros((len(xs), kbins), dtype=torch.float64, device=self.device)
+        self._check(self._L.ns_energy_spectrum(self._ctx, _ptrs(xs), ctypes.c_void_p(E.data_ptr()), int(kbins)))
+        return E
+
+    def profile(self, enable: bool = True):
+        self._check(self._L.ns_profile(self._ctx, 1 if enable else 0))
+
+    def profile_read(self):
+        """{pass name: (total ms, launches)} since the last read."""
+        ms = (ctypes.c_double * NS_NPASS)()
+        cnt = (ctypes.c_int64 * NS_NPASS)()
+        self._check(self._L.ns_profile_read(self._ctx, ms, cnt))
+        return {PASS_NAMES[p]: (ms[p], cnt[p]) for p in range(NS_NPASS)}
+
+    def workspace_bytes(self) -> int:
+        v = ctypes.c_size_t()
+        self._check(self._L.ns_workspace_bytes(self._ctx, ctypes.byref(v)))
+        return v.value
+
+    def sync(self):
+        self._check(self._L.ns_sync(self._ctx))
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._L.ns_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,69 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol
+that include/ns.h declares, and rejects bad arguments before touching the
+device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def ns():
+    from paper_2401_09843_amd import ns as m
+    if not os.path.exists(m.LIB_PATH):
+        pytest.fail("libns.so is not built; run __graft_entry__.build()")
+    m.lib()
+    return m
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "ns.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:ns_status|const char\*)\s+(ns_\w+)\s*\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol(ns):
+    syms = declared_symbols()
+    assert len(syms) >= 15
+    L = ns.lib()
+    for s in syms:
+        assert hasattr(L, s), s
+    assert sorted(ns.EXPORTS) == syms
+
+
+def test_supported_sizes(ns):
+    sizes = ns.supported_sizes()
+    assert 32 in sizes and 256 in sizes and 1024 in sizes
+    assert 48 in sizes and 80 in sizes  # radix 3 and 5
+
+
+def _params(ns, n, dtype=0, **kw):
+    nn = (ctypes.c_int32 * len(n))(*n)
+    p = ns._Params(dtype, len(n), nn, kw.get("eps", -1.0), kw.get("s", 1.5), kw.get("m_cut", -1.0),
+                   kw.get("q_kind", 0), kw.get("theta", 1.0), 0, None)
+    return p, nn
+
+
+def test_init_rejects_bad_arguments(ns):
+    L = ns.lib()
+    ctx = ctypes.c_void_p()
+    p, keep = _params(ns, [33])
+    assert L.ns_init(ctypes.byref(p), None, ctypes.byref(ctx)) == ns.NS_ERR_UNSUPPORTED
+    assert b"33" in L.ns_last_error(None)
+    p, keep = _params(ns, [32], dtype=7)
+    assert L.ns_init(ctypes.byref(p), None, ctypes.byref(ctx)) == ns.NS_ERR_ARG
+    p, keep = _params(ns, [32], q_kind=1, theta=0.0)
+    assert L.ns_init(ctypes.byref(p), None, ctypes.byref(ctx)) == ns.NS_ERR_ARG
+    assert L.ns_init(None, None, ctypes.byref(ctx)) == ns.NS_ERR_ARG
+    assert L.ns_init(ctypes.byref(p), None, None) == ns.NS_ERR_ARG
+    assert ctx.value is None
+    assert L.ns_destroy(None) == ns.NS_OK
+
+
+def test_calls_on_null_context_fail(ns):
+    L = ns.lib()
+    assert L.ns_rhs(None, None, None) == ns.NS_ERR_ARG
+    assert L.ns_step(None, None, None, 1) == ns.NS_ERR_ARG
+    assert L.ns_sync(None) == ns.NS_ERR_ARG
