@@ -483,3 +483,37 @@ double orc_div_rel(int n, const cplx *uh)
             }
     return den > 0.0 ? sqrt(num / den) : 0.0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Right-hand side of a field with a sparse spectrum, at chosen output modes,
+ * from the Galerkin definition (valid at any N because 3K < N):
+ *   b_i(k) = -i sum_j k_j sum_{p+q=k} u_i(p) u_j(q)   (p, q over the inputs),
+ *   c = (I - k k^T/|k|^2) b,  F(k) = c - eps |k|^{2s} Q u(k).
+ * kin[3*nin] / uin[3*nin] are the input modes (full spectrum: both k and -k
+ * of a real field must be listed) and their three components; kout[3*nout]
+ * the output modes (all inside T); out[3*nout] receives F. */
+void orc_rhs_sparse(const orc_params *p, int nin, const int *kin, const cplx *uin, int nout, const int *kout,
+                    cplx *out)
+{
+#pragma omp parallel for schedule(dynamic)
+    for (int o = 0; o < nout; ++o) {
+        const int *k = kout + 3 * o;
+        cplx b[3] = {0, 0, 0};
+        cplx uk[3] = {0, 0, 0};
+        for (int a = 0; a < nin; ++a) {
+            const int *pa = kin + 3 * a;
+            if (pa[0] == k[0] && pa[1] == k[1] && pa[2] == k[2])
+                for (int i = 0; i < 3; ++i) uk[i] = uin[3 * a + i];
+            for (int c = 0; c < nin; ++c) {
+                const int *qc = kin + 3 * c;
+                if (pa[0] + qc[0] != k[0] || pa[1] + qc[1] != k[1] || pa[2] + qc[2] != k[2]) continue;
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) b[i] += k[j] * uin[3 * a + i] * uin[3 * c + j];
+            }
+        }
+        for (int i = 0; i < 3; ++i) b[i] *= -I;
+        leray(k[0], k[1], k[2], &b[0], &b[1], &b[2]);
+        double rate = hyperviscous_rate(p, k[0], k[1], k[2]);
+        for (int i = 0; i < 3; ++i) out[3 * o + i] = b[i] - rate * uk[i];
+    }
+}

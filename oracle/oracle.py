@@ -82,6 +82,7 @@ def lib():
             "orc_adjoint_step": (None, [I, pp, P, D, P]),
             "orc_energy_spectrum": (None, [I, P, P, I]),
             "orc_div_rel": (D, [I, P]),
+            "orc_rhs_sparse": (None, [pp, I, P, P, I, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -220,3 +221,16 @@ def div_rel(uh: np.ndarray, n: int) -> float:
 
 def kcut(n: int) -> int:
     return (n - 1) // 3
+
+
+def rhs_sparse(modes: np.ndarray, coefs: np.ndarray, out_modes: np.ndarray, n: int, prm: Params = Params()):
+    """F at out_modes for a field whose full spectrum is nonzero only at
+    `modes` (int [m,3] as (kx,ky,kz), including the conjugate of every mode)
+    with coefficients coefs (complex [m,3]).  Galerkin triad sum."""
+    kin = np.ascontiguousarray(modes, dtype=np.int32)
+    uin = np.ascontiguousarray(coefs, dtype=np.complex128)
+    kout = np.ascontiguousarray(out_modes, dtype=np.int32)
+    out = np.zeros((len(kout), 3), dtype=np.complex128)
+    c = prm.c(n)
+    lib().orc_rhs_sparse(ctypes.byref(c), len(kin), _ptr(kin), _ptr(uin), len(kout), _ptr(kout), _ptr(out))
+    return out

@@ -187,6 +187,27 @@ struct Dft<16, DIR, T> {
     __device__ __forceinline__ static void run(cpx<T>* v) { DftSplit<4, 4, DIR, T>::run(v); }
 };
 
+// ---------------------------------------------------------------- helpers
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
+// with its own L2.  Renumber them so that every XCD walks one contiguous
+// range of tiles: neighbouring tiles, which share cache lines at their
+// edges, then run on the same XCD at about the same time.
+__device__ __forceinline__ long long xcd_tile(long long nb)
+{
+    const long long i = blockIdx.x;
+    const long long c = nb / 8, rem = nb % 8;
+    const long long x = i % 8, j = i / 8;
+    return x * c + (x < rem ? x : rem) + j;
+}
+
+// Copy the N-entry twiddle table to LDS (all threads of the block take part).
+template <typename T>
+__device__ __forceinline__ void load_twiddles(cpx<T>* dst, const cpx<T>* __restrict__ src, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------- plans
 template <int... Rs>
 struct Radices;
@@ -213,17 +234,39 @@ __device__ __forceinline__ int lds_pos(int pos) { return pos + pos / PD; }
 // Stage s of a transform of length N held by G threads: compute the
 // butterflies, then (unless it is the last stage) exchange through LDS into
 // the register layout of the next stage.  lds points at this line's slot 0;
-// element pos lives at lds[lds_pos<PD>(pos) * LS].
-template <int N, int G, int DIR, int PD, int LS, typename T, int P, int... Rs>
+// element pos lives at lds[lds_pos<PD>(pos) * LS].  With SP = 1 the
+// exchange moves the real and then the imaginary parts through a real-valued
+// buffer of the same layout (half the LDS, twice the barriers).
+template <int N, int G, int DIR, int PD, int LS, int SP, typename T, int P, int... Rs>
 struct Stages;
 
-template <int N, int G, int DIR, int PD, int LS, typename T, int P, int R, int... Rest>
-struct Stages<N, G, DIR, PD, LS, T, P, R, Rest...> {
+template <int N, int G, int DIR, int PD, int LS, int SP, typename T, int P, int R, int... Rest>
+struct Stages<N, G, DIR, PD, LS, SP, T, P, R, Rest...> {
     static constexpr int E = N / G;
     static constexpr int NB = N / (R * G);
     static_assert(NB * R * G == N, "G must divide N / R for every radix");
 
-    __device__ __forceinline__ static void run(cpx<T> (&v)[E], int t, cpx<T>* lds, const cpx<T>* __restrict__ tw)
+    template <int R2, typename L, typename Get, typename Put>
+    __device__ __forceinline__ static void exchange(cpx<T> (&v)[E], int t, L* lds, Get get, Put put)
+    {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int b = t + q * G;
+            const int k = b % P;
+            const int j = (b - k) * R + k;
+#pragma unroll
+            for (int m = 0; m < R; ++m) lds[lds_pos<PD>(j + m * P) * LS] = get(v[q * R + m]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < N / (R2 * G); ++q)
+#pragma unroll
+            for (int m = 0; m < R2; ++m) put(v[q * R2 + m], lds[lds_pos<PD>(t + q * G + m * (N / R2)) * LS]);
+        __syncthreads();
+    }
+
+    template <typename L>
+    __device__ __forceinline__ static void run(cpx<T> (&v)[E], int t, L* lds, const cpx<T>* __restrict__ tw)
     {
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
@@ -237,21 +280,14 @@ struct Stages<N, G, DIR, PD, LS, T, P, R, Rest...> {
         }
         if constexpr (sizeof...(Rest) > 0) {
             constexpr int R2 = Radices<Rest...>::first;
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                const int b = t + q * G;
-                const int k = b % P;
-                const int j = (b - k) * R + k;
-#pragma unroll
-                for (int m = 0; m < R; ++m) lds[lds_pos<PD>(j + m * P) * LS] = v[q * R + m];
+            if constexpr (SP == 0) {
+                exchange<R2>(v, t, lds, [](cpx<T> a) { return a; }, [](cpx<T>& d, cpx<T> a) { d = a; });
+            } else {
+                T* l = reinterpret_cast<T*>(lds);
+                exchange<R2>(v, t, l, [](cpx<T> a) { return a.x; }, [](cpx<T>& d, T a) { d.x = a; });
+                exchange<R2>(v, t, l, [](cpx<T> a) { return a.y; }, [](cpx<T>& d, T a) { d.y = a; });
             }
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < N / (R2 * G); ++q)
-#pragma unroll
-                for (int m = 0; m < R2; ++m) v[q * R2 + m] = lds[lds_pos<PD>(t + q * G + m * (N / R2)) * LS];
-            __syncthreads();
-            Stages<N, G, DIR, PD, LS, T, P * R, Rest...>::run(v, t, lds, tw);
+            Stages<N, G, DIR, PD, LS, SP, T, P * R, Rest...>::run(v, t, lds, tw);
         }
     }
 };
@@ -268,10 +304,10 @@ struct Plan<N_, G_, Radices<Rs...>> {
     // LDS elements per line (with padding)
     static constexpr int lds_len = N_ + N_ / R0 + 1;
 
-    template <int DIR, int LS, typename T>
+    template <int DIR, int LS, int SP = 0, typename T>
     __device__ __forceinline__ static void run(cpx<T> (&v)[E], int t, cpx<T>* lds, const cpx<T>* __restrict__ tw)
     {
-        Stages<N_, G_, DIR, R0, LS, T, 1, Rs...>::run(v, t, lds, tw);
+        Stages<N_, G_, DIR, R0, LS, SP, T, 1, Rs...>::run(v, t, lds, tw);
     }
     // position of register element i = q * R + m at stage-0 input / final output
     __device__ __forceinline__ static constexpr int in_pos(int t, int i) { return t + (i / R0) * G + (i % R0) * (N / R0); }

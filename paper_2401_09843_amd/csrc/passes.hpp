@@ -30,20 +30,28 @@ __device__ __forceinline__ int compact_of(int n, int N, int K, int M)
 }
 
 // ------------------------------------------------------------------ I1/I2/F2
-template <class P, int T, int DIR, int MODE, typename R>
+// LDS bytes of a column tile (complex or split exchange), 16-byte aligned
+template <class P, int T, int SP, typename R>
+constexpr size_t tile_bytes()
+{
+    return ((SP ? sizeof(R) : sizeof(cpx<R>)) * P::lds_len * T + 15) / 16 * 16;
+}
+
+template <class P, int T, int DIR, int MODE, int SP, typename R>
 __global__ void __launch_bounds__(P::G* T) k_colfft(ColArgs a)
 {
     constexpr int N = P::N, E = P::E;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
+    cpx<R>* twl = reinterpret_cast<cpx<R>*>(smem_raw + tile_bytes<P, T, SP, R>());
+    load_twiddles(twl, static_cast<const cpx<R>*>(a.tw), N);
     const int tid = threadIdx.x, c = tid % T, g = tid / T;
-    const long long q = (long long)blockIdx.x * T + c;
+    const long long q = xcd_tile(gridDim.x) * T + c;
     const bool valid = q < a.Q;
     const long long outer = valid ? q / a.S : 0;
     const long long inner = valid ? q % a.S : 0;
     const cpx<R>* __restrict__ in = static_cast<const cpx<R>*>(a.in) + outer * a.in_os + inner;
     cpx<R>* __restrict__ out = static_cast<cpx<R>*>(a.out) + outer * a.out_os + inner;
-    const cpx<R>* __restrict__ tw = static_cast<const cpx<R>*>(a.tw);
 
     cpx<R> v[E];
 #pragma unroll
@@ -53,7 +61,8 @@ __global__ void __launch_bounds__(P::G* T) k_colfft(ColArgs a)
         if constexpr (MODE == COL_INV_PAD) r = compact_of(n, N, a.K, a.M);
         v[i] = (valid && r >= 0) ? in[r * a.S] : cpx<R>{0, 0};
     }
-    P::template run<DIR, T>(v, g, lds + c, tw);
+    if constexpr (SP) P::template run<DIR, T, 1>(v, g, reinterpret_cast<cpx<R>*>(reinterpret_cast<R*>(lds) + c), twl);
+    else P::template run<DIR, T, 0>(v, g, lds + c, twl);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int n = P::out_pos(g, i);
@@ -79,15 +88,16 @@ __global__ void __launch_bounds__(PI::G* U) k_xline(XArgs a)
     static_assert(PF::R0 == PI::RL, "forward plan must start with the inverse plan's last radix");
     constexpr int LL = PI::lds_len > PF::lds_len ? PI::lds_len : PF::lds_len;
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<R>* tw = reinterpret_cast<cpx<R>*>(smem_raw) + U * LL;
+    load_twiddles(tw, static_cast<const cpx<R>*>(a.tw), N);
     const int tid = threadIdx.x, u = tid / G, t = tid % G;
     cpx<R>* my = reinterpret_cast<cpx<R>*>(smem_raw) + u * LL;
-    const long long unit = (long long)blockIdx.x * U + u;
+    const long long unit = xcd_tile(gridDim.x) * U + u;
     const bool valid = unit < a.nunits;
     const long long L = valid ? 2 * unit : 0;
     const long long samp = L / ((long long)N * N);
     const long long l1 = L % ((long long)N * N);
     const int K = a.K, Mx = K + 1;
-    const cpx<R>* __restrict__ tw = static_cast<const cpx<R>*>(a.tw);
 
     // inverse (C2R) of component c of both lines into z = a + i b
     auto load_inv = [&](int c, cpx<R>(&v)[E]) {
@@ -185,15 +195,17 @@ __global__ void __launch_bounds__(PI::G* U) k_xline(XArgs a)
 }
 
 // ------------------------------------------------------------------ F3 pass
-template <class P, int T, int MODE, typename R>
+template <class P, int T, int MODE, int SP, typename R>
 __global__ void __launch_bounds__(P::G* T) k_f3(F3Args a)
 {
     constexpr int N = P::N, E = P::E;
     constexpr int NC = MODE == F3_RHS ? 6 : 3;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
+    cpx<R>* twl = reinterpret_cast<cpx<R>*>(smem_raw + tile_bytes<P, T, SP, R>());
+    load_twiddles(twl, static_cast<const cpx<R>*>(a.tw), N);
     const int tid = threadIdx.x, c = tid % T, g = tid / T;
-    const long long q = (long long)blockIdx.x * T + c;
+    const long long q = xcd_tile(gridDim.x) * T + c;
     const bool valid = q < a.Q;
     const long long samp = valid ? q / a.MMx : 0;
     const int s = valid ? (int)(q % a.MMx) : 0;
@@ -202,7 +214,6 @@ __global__ void __launch_bounds__(P::G* T) k_f3(F3Args a)
     const int kyi = jy <= K ? jy : jy - M;
     const R kx = (R)kxi, ky = (R)kyi;
     const cpx<R>* __restrict__ in = static_cast<const cpx<R>*>(a.in) + samp * a.in_ss + s;
-    const cpx<R>* __restrict__ tw = static_cast<const cpx<R>*>(a.tw);
 
     cpx<R> acc[3][E];
 #pragma unroll
@@ -218,7 +229,8 @@ __global__ void __launch_bounds__(P::G* T) k_f3(F3Args a)
             const int n = P::in_pos(g, i);
             v[i] = valid ? in[p * a.in_cs + (long long)n * a.MMx] : cpx<R>{0, 0};
         }
-        P::template run<-1, T>(v, g, lds + c, tw);
+        if constexpr (SP) P::template run<-1, T, 1>(v, g, reinterpret_cast<cpx<R>*>(reinterpret_cast<R*>(lds) + c), twl);
+        else P::template run<-1, T, 0>(v, g, lds + c, twl);
         if constexpr (MODE == F3_RHS) {
             // component p = (i, j) of the upper triangle adds k_j B to b_i
             // and, off the diagonal, k_i B to b_j: b_r += (wxy_r + wz_r k_z) B
@@ -345,33 +357,35 @@ struct Launch {
     static constexpr int T = f64 ? C::T64 : C::T32;
     static constexpr int TF = f64 ? C::TF64 : C::TF32;
     static constexpr int U = f64 ? C::U64 : C::U32;
+    static constexpr int SP = f64 ? C::SP64 : C::SP32;
+    static constexpr int SPF = f64 ? C::SPF64 : C::SPF32;
     static constexpr int XL = PX::lds_len > PXR::lds_len ? PX::lds_len : PXR::lds_len;
 
     static hipError_t col_inv(const ColArgs& a, hipStream_t s)
     {
         static bool done = false;
-        return launch_k(k_colfft<P, T, +1, COL_INV_PAD, R>, (a.Q + T - 1) / T, C::G * T,
-                        sizeof(cpx<R>) * P::lds_len * T, s, a, done);
+        return launch_k(k_colfft<P, T, +1, COL_INV_PAD, SP, R>, (a.Q + T - 1) / T, C::G * T,
+                        tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * N, s, a, done);
     }
     static hipError_t col_fwd(const ColArgs& a, hipStream_t s)
     {
         static bool done = false;
-        return launch_k(k_colfft<P, T, -1, COL_FWD_TRUNC, R>, (a.Q + T - 1) / T, C::G * T,
-                        sizeof(cpx<R>) * P::lds_len * T, s, a, done);
+        return launch_k(k_colfft<P, T, -1, COL_FWD_TRUNC, SP, R>, (a.Q + T - 1) / T, C::G * T,
+                        tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * N, s, a, done);
     }
     template <int MODE>
     static hipError_t xl(const XArgs& a, hipStream_t s)
     {
         static bool done = false;
-        return launch_k(k_xline<PX, PXR, U, MODE, R>, (a.nunits + U - 1) / U, C::GX * U, sizeof(cpx<R>) * XL * U, s,
-                        a, done);
+        return launch_k(k_xline<PX, PXR, U, MODE, R>, (a.nunits + U - 1) / U, C::GX * U,
+                        sizeof(cpx<R>) * (XL * U + N), s, a, done);
     }
     template <int MODE>
     static hipError_t f3(const F3Args& a, hipStream_t s)
     {
         static bool done = false;
-        return launch_k(k_f3<PF, TF, MODE, R>, (a.Q + TF - 1) / TF, C::GF * TF, sizeof(cpx<R>) * PF::lds_len * TF, s,
-                        a, done);
+        return launch_k(k_f3<PF, TF, MODE, SPF, R>, (a.Q + TF - 1) / TF, C::GF * TF,
+                        tile_bytes<PF, TF, SPF, R>() + sizeof(cpx<R>) * N, s, a, done);
     }
     static SizeKernels make()
     {

@@ -164,3 +164,42 @@ def shear_layer_torch(n: int, seed: int = 0, rho: float = 0.05, delta=0.025, nmo
                 u[comp].add_(c, alpha=float(delta * a[comp]))
         del c
     return u, float(delta), modes
+
+
+def sparse_modes(n: int, seed: int, count: int = 24, kmax=None):
+    """A seeded real field with a sparse spectrum: `count` random wave
+    vectors in the cube |k_i| <= kmax (default the 2/3 cutoff floor((N-1)/3),
+    edges included) with k_x >= 0, random complex amplitudes, plus the
+    conjugate partner of each.  Returns (modes int [m,3] as (kx,ky,kz),
+    coefs complex [m,3]) listing the full spectrum."""
+    K = (n - 1) // 3 if kmax is None else kmax
+    rng = np.random.default_rng(seed)
+    chosen = {}
+    edges = [K, -K, K - 1, 1, 0]
+    while len(chosen) < count:
+        if len(chosen) < 6:  # some modes on the cutoff edges
+            k = (int(rng.choice([K, K - 1, 1])), int(rng.choice(edges)), int(rng.choice(edges)))
+        else:
+            k = (int(rng.integers(0, K + 1)), int(rng.integers(-K, K + 1)), int(rng.integers(-K, K + 1)))
+        if k == (0, 0, 0):
+            continue
+        if k[0] == 0 and (-k[0], -k[1], -k[2]) in chosen:
+            continue
+        chosen[k] = (rng.standard_normal(3) + 1j * rng.standard_normal(3)) / np.sqrt(2 * count)
+    modes, coefs = [], []
+    for k, c in chosen.items():
+        modes.append(k)
+        coefs.append(c)
+        modes.append((-k[0], -k[1], -k[2]))
+        coefs.append(np.conj(c))
+    return np.array(modes, dtype=np.int64), np.array(coefs)
+
+
+def sparse_to_half_spectrum(n: int, modes: np.ndarray, coefs: np.ndarray) -> np.ndarray:
+    """Scatter a sparse full spectrum into the half-spectrum layout
+    [3][N][N][N/2+1] (entries with k_x >= 0 only)."""
+    h = np.zeros((3, n, n, n // 2 + 1), dtype=np.complex128)
+    for (kx, ky, kz), c in zip(modes, coefs):
+        if kx >= 0:
+            h[:, kz % n, ky % n, kx] = c
+    return h

@@ -1,0 +1,101 @@
+"""Parity at the benchmark sizes (512^3, 1024^3 FP32; 256^3 FP64), in the
+launch configuration the benchmark uses.  The oracle cannot transform these
+grids, so the inputs have sparse spectra: the Galerkin triad sum of the
+oracle then gives the exact right-hand side at every output mode, and the
+GPU result is compared mode by mode, with everything off that support
+checked to be rounding noise.  Time stepping is checked at full size on a
+helical mode, whose nonlinear term is a pure gradient, so n steps multiply
+it by R(z)^n with R the SSP-RK3 amplification polynomial."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2401_09843_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ns():
+    from paper_2401_09843_amd import ns as m
+    assert torch.cuda.is_available()
+    m.lib()
+    return m
+
+
+def out_support(modes, K):
+    """All sums p + q of input modes inside the cube, plus the inputs; k_x >= 0."""
+    s = set()
+    for p in modes:
+        for q in modes:
+            k = p + q
+            if k[0] >= 0 and np.all(np.abs(k) <= K):
+                s.add(tuple(int(v) for v in k))
+        if p[0] >= 0:
+            s.add(tuple(int(v) for v in p))
+    return np.array(sorted(s), dtype=np.int64)
+
+
+@pytest.mark.parametrize("n,dtype,tol", [(256, torch.float64, 1e-12), (512, torch.float32, 1e-5),
+                                         (1024, torch.float32, 1e-5)])
+def test_sparse_rhs_full_size(ns, orc, n, dtype, tol):
+    print("sparse rhs n=%d %s" % (n, dtype), flush=True)
+    modes, coefs = inputs.sparse_modes(n, seed=n + 7, count=24)
+    K = (n - 1) // 3
+    kout = out_support(modes, K)
+    prm = orc.Params()
+    ref = orc.rhs_sparse(modes, coefs, kout, n, prm)  # [m, 3]
+    cd = torch.complex64 if dtype == torch.float32 else torch.complex128
+    S = ns.Solver(n, dtype=dtype)
+    uh = torch.zeros((3, n, n, n // 2 + 1), dtype=cd, device="cuda")
+    sel = modes[:, 0] >= 0
+    iz = torch.as_tensor(modes[sel, 2] % n, device="cuda")
+    iy = torch.as_tensor(modes[sel, 1] % n, device="cuda")
+    ix = torch.as_tensor(modes[sel, 0], device="cuda")
+    vals = torch.as_tensor(coefs[sel].T.copy(), device="cuda").to(cd)
+    for c in range(3):
+        uh[c, iz, iy, ix] = vals[c]
+    F = S.rhs(uh)
+    del uh
+    oz = torch.as_tensor(kout[:, 2] % n, device="cuda")
+    oy = torch.as_tensor(kout[:, 1] % n, device="cuda")
+    ox = torch.as_tensor(kout[:, 0], device="cuda")
+    got = torch.stack([F[c, oz, oy, ox] for c in range(3)], dim=1).cpu().numpy().astype(np.complex128)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    # every half-spectrum entry on the support is gathered exactly once (on
+    # the k_x = 0 plane both k and -k are entries and both are in kout)
+    total = float(torch.sum(torch.abs(F.to(torch.complex128)) ** 2).item())
+    on = float(np.sum(np.abs(got) ** 2))
+    off = max(total - on, 0.0) / max(total, 1e-300)
+    print("n=%d rel err %.3e, off-support fraction %.3e" % (n, err, off), flush=True)
+    assert err <= tol
+    assert off <= tol ** 2 * 10
+    del F
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n", [512, 1024])
+def test_helical_decay_full_size(ns, n):
+    """F = -eps |k|^{2s} u for a single helical mode above m_N; n RK3 steps
+    multiply it by R(z)^n, z = -dt eps |k|^{2s}."""
+    print("helical decay n=%d" % n, flush=True)
+    kvec = np.array([n // 3 - 2, n // 4, -(n // 5)])
+    kk = float(kvec @ kvec)
+    eps = 1e-3 * (32.0 / n) ** 2
+    dt, steps = 0.4 / (eps * kk ** 1.5), 3
+    S = ns.Solver(n, dtype=torch.float32)
+    # helical mode with amplitude h: h is orthogonal to k and i k x h = |k| h
+    kn = kvec / np.sqrt(kk)
+    a = np.cross(kn, [1.0, 0.0, 0.0])
+    a /= np.linalg.norm(a)
+    b = np.cross(kn, a)
+    h = 0.5 * (a - 1j * b)
+    uh = torch.zeros((3, n, n, n // 2 + 1), dtype=torch.complex64, device="cuda")
+    uh[:, kvec[2] % n, kvec[1] % n, kvec[0]] = torch.as_tensor(h, device="cuda").to(torch.complex64)
+    ref = uh.clone()
+    S.step(uh, dt, steps)
+    zeta = -dt * eps * kk ** 1.5
+    R = 1 + zeta + zeta ** 2 / 2 + zeta ** 3 / 6
+    err = float(torch.linalg.vector_norm(uh - R ** steps * ref).item() / torch.linalg.vector_norm(R ** steps * ref).item())
+    print("n=%d helical decay rel err %.3e (R^n = %.4f)" % (n, err, R ** steps), flush=True)
+    assert err <= 1e-5

@@ -221,3 +221,19 @@ def test_energy_spectrum_parseval_and_shells(orc):
     expect = np.zeros(10)
     expect[5] = 1.0
     assert np.max(np.abs(E - expect)) <= 1e-14
+
+
+@pytest.mark.parametrize("n", [12, 16, 24])
+def test_sparse_triad_rhs_matches_pseudo_spectral(orc, n):
+    # the sparse Galerkin evaluation against the full pseudo-spectral RHS
+    modes, coefs = inputs.sparse_modes(n, seed=n, count=10)
+    uh = inputs.sparse_to_half_spectrum(n, modes, coefs)
+    prm = orc.Params(eps=3e-3, m_cut=2.5)
+    full = orc.rhs(uh, n, prm)
+    K = orc.kcut(n)
+    ks = np.arange(-K, K + 1)
+    outm = np.array([(a, b, c) for a in range(0, K + 1) for b in ks for c in ks])
+    got = orc.rhs_sparse(modes, coefs, outm, n, prm)
+    ref = np.stack([full[:, c % n, b % n, a] for a, b, c in outm])
+    assert np.max(np.abs(got - ref)) <= 1e-14 * max(1.0, np.max(np.abs(ref)))
+    assert np.max(np.abs(ref)) > 1e-3
