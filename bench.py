@@ -41,6 +41,78 @@ def cpu_baseline(n_sample: int = 128):
             "sample": "one SSP-RK3 step (3 RHS) of the seed-0 shear layer at %d^3, FP64, %.1f s" % (n_sample, t)}
 
 
+def run_ensemble(args):
+    """Statistical-solution ensemble: 64 samples at 128^3 and 32 at 64^3,
+    FP32, seeds 1000+i, delta ~ U[0.01, 0.05], per-sample CFL dt, batched in
+    one context (one launch per pass per grid size, graph-replayed steps)
+    against looping single-sample solvers over the same samples."""
+    import torch
+
+    from paper_2401_09843_amd import inputs, ns
+
+    steps = args.steps
+    sizes = [128] * 64 + [64] * 32
+    dev = torch.device("cuda", 0)
+    fields, dts = [], []
+    for i, n in enumerate(sizes):
+        u, _, _ = inputs.shear_layer_torch(n, seed=1000 + i, delta=(0.01, 0.05), device=dev, dtype=torch.float32)
+        fields.append(u)
+        dts.append(float(0.5 * (2 * 3.141592653589793 / n) / u.abs().sum(0).max().item()))
+    print("ensemble: %d samples, %d steps" % (len(sizes), steps), file=sys.stderr, flush=True)
+    E = ns.Solver(sizes, dtype=torch.float32, graph=True, tune=not args.no_tune)
+    uhs = E.forward(fields)
+    init = [t.clone() for t in uhs]
+    E.step(uhs, dts, args.warmup)
+    for t, t0 in zip(uhs, init):
+        t.copy_(t0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E.step(uhs, dts, steps)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    # looping the plain solver (one context per grid size, one sample at a time)
+    plain = {n: ns.Solver(n, dtype=torch.float32, graph=True, tune=not args.no_tune) for n in sorted(set(sizes))}
+    loop = [t.clone() for t in init]
+    for i, n in enumerate(sizes[:2]):
+        plain[n].step(init[i].clone(), dts[i], args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, n in enumerate(sizes):
+        plain[n].step(loop[i], dts[i], steps)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    worst = 0.0
+    for a, b in zip(uhs, loop):
+        d = torch.linalg.vector_norm(a - b).item() / torch.linalg.vector_norm(b).item()
+        worst = max(worst, d)
+    kb = 112
+    spec = E.spectrum(uhs, kb)
+    mean128 = spec[:64].mean(0).cpu().tolist()
+    mean64 = spec[64:].mean(0).cpu().tolist()
+    out = {
+        "metric": "ensemble samples/s (96 samples: 64x128^3 + 32x64^3, 200 SSP-RK3 steps)",
+        "value": len(sizes) / t_batched * (200.0 / steps),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_batched / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: seeded shear layers, seeds 1000+i, delta ~ U[0.01,0.05]",
+        "config": {"workload": "ensemble 64x128^3 + 32x64^3 FP32", "parallelism": "single GPU"},
+        "looped_plain_samples_per_s": len(sizes) / t_loop * (200.0 / steps),
+        "speedup_vs_loop": t_loop / t_batched,
+        "max_rel_diff_batched_vs_loop": worst,
+        "mean_E_k_128": mean128[:44],
+        "mean_E_k_64": mean64[:38],
+        "schedule": E.tune_report(),
+    }
+    print(json.dumps(out))
+
+
 def measured_traffic(kernel: str, n: int):
     """HBM bytes per launch from committed rocprofv3 PMC summaries, if any."""
     path = os.path.join(PROFILE_DIR, "traffic_%s_n%d.json" % (kernel, n))
@@ -60,6 +132,8 @@ def main():
     ap.add_argument("--dtype", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="use the built-in schedules instead of the autotuner")
+    ap.add_argument("--ensemble", action="store_true", help="run the 96-sample ensemble workload instead")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 2 GiB three times (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -79,6 +153,10 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_read": src.numel() * 4, "bytes_written": dst.numel() * 4, "launches": 3}))
         return
 
+    if args.ensemble:
+        run_ensemble(args)
+        return
+
     from paper_2401_09843_amd import inputs, ns, perfmodel
 
     n = args.n
@@ -88,7 +166,9 @@ def main():
     torch.cuda.set_device(dev)
     print("bench: n=%d %s steps=%d warmup=%d" % (n, args.dtype, args.steps, args.warmup), file=sys.stderr, flush=True)
 
-    S = ns.Solver(n, dtype=dt_torch, graph=True)
+    S = ns.Solver(n, dtype=dt_torch, graph=True, tune=not args.no_tune)
+    schedule = {r["pass"]: r["selected"] for r in S.tune_report()}
+    print("bench: schedule %s" % json.dumps(S.tune_report()), file=sys.stderr, flush=True)
     u0, _, _ = inputs.shear_layer_torch(n, seed=0, device=dev, dtype=dt_torch)
     dt = float(0.5 * (2.0 * 3.141592653589793 / n) / u0.abs().sum(dim=0).max().item())
     uh = S.forward(u0)
@@ -152,6 +232,7 @@ def main():
         "step_roofline_frac": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "roofline": roofline,
         "passes": per_pass,
+        "schedule": schedule,
         "finite": finite,
         "cpu_baseline": cpu,
     }

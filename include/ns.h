@@ -171,6 +171,20 @@ ns_status ns_sync(ns_ctx* ctx);
 ns_status ns_profile(ns_ctx* ctx, int32_t enable);
 ns_status ns_profile_read(ns_ctx* ctx, double* ms, int64_t* count);
 
+/* Schedule variants and the autotuner (the build's analogue of the per-
+ * system FFT benchmark of Sec. 3.1).  Each pass of the samples of grid size
+ * n has a list of compiled schedules (threads per line, radix order, tile
+ * width, LDS exchange form, occupancy); all compute the same result.
+ * Unless NS_NO_TUNE is set, ns_init times every variant on the context's
+ * workspaces, keeps the fastest, and appends the choice to the tune_cache
+ * file (one JSON object per line; read back when the key matches).
+ * ns_set_variant overrides the choice (e.g. to test every variant);
+ * ns_tune_report writes the choices and timings as JSON into buf (always
+ * NUL-terminated; *needed receives the full length + 1). */
+ns_status ns_variant_count(ns_ctx* ctx, int32_t n, int32_t pass, int32_t* count);
+ns_status ns_set_variant(ns_ctx* ctx, int32_t n, int32_t pass, int32_t variant);
+ns_status ns_tune_report(ns_ctx* ctx, char* buf, size_t len, size_t* needed);
+
 #ifdef __cplusplus
 }
 #endif

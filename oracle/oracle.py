@@ -234,3 +234,23 @@ def rhs_sparse(modes: np.ndarray, coefs: np.ndarray, out_modes: np.ndarray, n: i
     c = prm.c(n)
     lib().orc_rhs_sparse(ctypes.byref(c), len(kin), _ptr(kin), _ptr(uin), len(kout), _ptr(kout), _ptr(out))
     return out
+
+
+def rollout_gradient(u0: np.ndarray, dt: float, nsteps: int, weight: np.ndarray, prm: Params = Params()):
+    """Reference gradient of J = 1/2 sum over the full spectrum of
+    weight_k |u-hat_k(T)|^2 with respect to the physical u0, through
+    u-hat(0) = T P F[u0] and nsteps SSP-RK3 steps; weight is a half-spectrum
+    [N][N][N/2+1] real mask.  Returns (J, grad [3][N]^3)."""
+    n = u0.shape[-1]
+    states = [initial_state(u0, prm)]
+    for _ in range(nsteps):
+        states.append(ssprk3(states[-1], n, dt, 1, prm))
+    uT = states[-1]
+    wfull = np.real(full_from_r2c(weight[None].astype(np.complex128), n))[0]
+    full = full_from_r2c(uT, n)
+    J = 0.5 * float(np.sum(wfull[None] * np.abs(full) ** 2))
+    lam = uT * weight[None]
+    for k in range(nsteps - 1, -1, -1):
+        lam = adjoint_step(states[k], lam, n, dt, prm)
+    mu = project(lam, n, prm)
+    return J, inverse(mu, n) / n ** 3

@@ -20,8 +20,8 @@
 namespace ns {
 
 enum { COL_INV_PAD = 0, COL_FWD_TRUNC = 1 };
-enum { X_RHS = 0, X_FWD3 = 1, X_INV3 = 2 };
-enum { F3_RHS = 0, F3_PROJ = 1 };
+enum { X_RHS = 0, X_FWD3 = 1, X_INV3 = 2, X_ADJ = 3 };
+enum { F3_RHS = 0, F3_PROJ = 1, F3_ADJ = 2 };
 
 // compact index of FFT row n (wavenumber n or n - N), or -1 outside |k| <= K
 __device__ __forceinline__ int compact_of(int n, int N, int K, int M)
@@ -37,8 +37,8 @@ constexpr size_t tile_bytes()
     return ((SP ? sizeof(R) : sizeof(cpx<R>)) * P::lds_len * T + 15) / 16 * 16;
 }
 
-template <class P, int T, int DIR, int MODE, int SP, typename R>
-__global__ void __launch_bounds__(P::G* T) k_colfft(ColArgs a)
+template <class P, int T, int DIR, int MODE, int SP, int W, typename R>
+__global__ void __launch_bounds__(P::G* T, W) k_colfft(ColArgs a)
 {
     constexpr int N = P::N, E = P::E;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -50,8 +50,9 @@ __global__ void __launch_bounds__(P::G* T) k_colfft(ColArgs a)
     const bool valid = q < a.Q;
     const long long outer = valid ? q / a.S : 0;
     const long long inner = valid ? q % a.S : 0;
-    const cpx<R>* __restrict__ in = static_cast<const cpx<R>*>(a.in) + outer * a.in_os + inner;
-    cpx<R>* __restrict__ out = static_cast<cpx<R>*>(a.out) + outer * a.out_os + inner;
+    const long long sb = outer / a.nc, pc = outer % a.nc;
+    const cpx<R>* __restrict__ in = static_cast<const cpx<R>*>(a.in) + sb * a.in_ss + pc * a.in_cs + inner;
+    cpx<R>* __restrict__ out = static_cast<cpx<R>*>(a.out) + sb * a.out_ss + pc * a.out_cs + inner;
 
     cpx<R> v[E];
 #pragma unroll
@@ -80,8 +81,8 @@ __global__ void __launch_bounds__(P::G* T) k_colfft(ColArgs a)
 // Z = A + iB with A, B the Hermitian half spectra gives z = a + i b; for an
 // R2C, Z = FFT(a + i b) splits as A_k = (Z_k + conj Z_{N-k})/2,
 // B_k = (Z_k - conj Z_{N-k})/(2i).
-template <class PI, class PF, int U, int MODE, typename R>
-__global__ void __launch_bounds__(PI::G* U) k_xline(XArgs a)
+template <class PI, class PF, int U, int MODE, int W, typename R>
+__global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
 {
     constexpr int N = PI::N, G = PI::G, E = PI::E;
     static_assert(PF::G == G && PF::N == N, "plans must match");
@@ -166,6 +167,38 @@ __global__ void __launch_bounds__(PI::G* U) k_xline(XArgs a)
             }
             fwd_store(p, v);
         }
+    } else if constexpr (MODE == X_ADJ) {
+        // inputs: components 0..5 the strain S (xx, xy, xz, yy, yz, zz),
+        // 6..8 the velocity; a_i = 2 sum_j S_ij u_j, upper triangle (i, j)
+        // adds S_ij u_j to a_i and, off the diagonal, S_ij u_i to a_j
+        cpx<R> u0[E], u1[E], u2[E], a0[E], a1[E], a2[E], v[E];
+        load_inv(6, u0);
+        load_inv(7, u1);
+        load_inv(8, u2);
+#pragma unroll
+        for (int i = 0; i < E; ++i) a0[i] = a1[i] = a2[i] = cpx<R>{0, 0};
+        auto fma2 = [&](cpx<R>(&acc)[E], const cpx<R>(&s)[E], const cpx<R>(&w)[E]) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                acc[i].x += (R)2 * s[i].x * w[i].x;
+                acc[i].y += (R)2 * s[i].y * w[i].y;
+            }
+        };
+#pragma unroll 1
+        for (int p = 0; p < 6; ++p) {
+            load_inv(p, v);
+            switch (p) {
+                case 0: fma2(a0, v, u0); break;
+                case 1: fma2(a0, v, u1); fma2(a1, v, u0); break;
+                case 2: fma2(a0, v, u2); fma2(a2, v, u0); break;
+                case 3: fma2(a1, v, u1); break;
+                case 4: fma2(a1, v, u2); fma2(a2, v, u1); break;
+                default: fma2(a2, v, u2); break;
+            }
+        }
+        fwd_store(0, a0);
+        fwd_store(1, a1);
+        fwd_store(2, a2);
     } else if constexpr (MODE == X_INV3) {
         cpx<R> v[E];
         for (int c = 0; c < 3; ++c) {
@@ -195,11 +228,11 @@ __global__ void __launch_bounds__(PI::G* U) k_xline(XArgs a)
 }
 
 // ------------------------------------------------------------------ F3 pass
-template <class P, int T, int MODE, int SP, typename R>
-__global__ void __launch_bounds__(P::G* T) k_f3(F3Args a)
+template <class P, int T, int MODE, int SP, int W, typename R>
+__global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
 {
     constexpr int N = P::N, E = P::E;
-    constexpr int NC = MODE == F3_RHS ? 6 : 3;
+    constexpr int NC = MODE == F3_RHS ? 6 : 3;  // F3_PROJ and F3_ADJ take 3 components
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     cpx<R>* twl = reinterpret_cast<cpx<R>*>(smem_raw + tile_bytes<P, T, SP, R>());
@@ -269,7 +302,7 @@ __global__ void __launch_bounds__(P::G* T) k_f3(F3Args a)
     }
 
     const R sc = (R)a.scale;
-    const double dts = (MODE == F3_RHS && valid) ? a.dt[samp] : 0.0;
+    const double dts = (MODE != F3_PROJ && valid) ? a.dt[samp] : 0.0;
     const R* __restrict__ rate = static_cast<const R*>(a.rate);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
@@ -285,6 +318,36 @@ __global__ void __launch_bounds__(P::G* T) k_f3(F3Args a)
             else b[j] = {acc[j][i].x * sc, acc[j][i].y * sc};
         }
         const int k2 = kxi * kxi + kyi * kyi + kzi * kzi;
+        const long long st = samp * a.st_ss + (long long)jz * a.MMx + s;
+        if constexpr (MODE == F3_ADJ) {
+            // out = ca L3 + c2 L2 + c1 L1 + cc dt (T a - rate lam), no projection
+            const R rt = rate[k2];
+            const R c3 = (R)a.ca, c2 = (R)a.c2, c1 = (R)a.c1, cdt = (R)(a.cc * dts);
+            const cpx<R>* lam = static_cast<const cpx<R>*>(a.us) + st;
+            cpx<R>* o = static_cast<cpx<R>*>(a.out) + st;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const cpx<R> w = lam[j * a.st_cs];
+                cpx<R> r = {cdt * (b[j].x - rt * w.x), cdt * (b[j].y - rt * w.y)};
+                if (a.ca != 0.0) {
+                    const cpx<R> z = static_cast<const cpx<R>*>(a.u0)[st + j * a.st_cs];
+                    r.x += c3 * z.x;
+                    r.y += c3 * z.y;
+                }
+                if (a.c2 != 0.0) {
+                    const cpx<R> z = static_cast<const cpx<R>*>(a.l2)[st + j * a.st_cs];
+                    r.x += c2 * z.x;
+                    r.y += c2 * z.y;
+                }
+                if (a.c1 != 0.0) {
+                    const cpx<R> z = static_cast<const cpx<R>*>(a.l1)[st + j * a.st_cs];
+                    r.x += c1 * z.x;
+                    r.y += c1 * z.y;
+                }
+                o[j * a.st_cs] = r;
+            }
+            continue;
+        }
         if (k2 > 0) {
             const R inv = (R)1 / (R)k2;
             const cpx<R> kb = {kx * b[0].x + ky * b[1].x + kz * b[2].x, kx * b[0].y + ky * b[1].y + kz * b[2].y};
@@ -295,7 +358,6 @@ __global__ void __launch_bounds__(P::G* T) k_f3(F3Args a)
                 b[j].y -= kv[j] * kb.y * inv;
             }
         }
-        const long long st = samp * a.st_ss + (long long)jz * a.MMx + s;
         if constexpr (MODE == F3_RHS) {
             const R rt = rate[k2];
             const R ca = (R)a.ca, cb = (R)a.cb, cdt = (R)(a.cc * dts);
@@ -338,11 +400,51 @@ inline hipError_t launch_k(void (*k)(Args), long long blocks, int threads, size_
     return hipGetLastError();
 }
 
-// Per-size schedule: each pass has its own line plan (threads per line and
-// radix order): the column passes (G, Rad), the x pass (GX, XRad and its
-// reverse XRadRev for the forward half) and the fused z pass (GF, FRad);
-// T / TF columns per block for the column and fused z passes and U line
-// pairs per block for the x pass, for FP32 and FP64.
+// Launchers of one schedule each.  W is the minimum number of waves per
+// SIMD the compiler must allow (it caps the registers per thread).
+template <class P, int T, int DIR, int MODE, int SP, int W, typename R>
+hipError_t launch_col(const ColArgs& a, hipStream_t s)
+{
+    static_assert(P::G * T <= 1024, "at most 1024 threads per block");
+    static_assert(tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::N <= 163840, "LDS per block exceeds 160 KiB");
+    static bool done = false;
+    return launch_k(k_colfft<P, T, DIR, MODE, SP, W, R>, (a.Q + T - 1) / T, P::G * T,
+                    tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::N, s, a, done);
+}
+
+template <class PI, class PF, int U, int MODE, int W, typename R>
+hipError_t launch_x(const XArgs& a, hipStream_t s)
+{
+    constexpr int XL = PI::lds_len > PF::lds_len ? PI::lds_len : PF::lds_len;
+    static_assert(PI::G * U <= 1024, "at most 1024 threads per block");
+    static_assert(sizeof(cpx<R>) * (XL * U + PI::N) <= 163840, "LDS per block exceeds 160 KiB");
+    static bool done = false;
+    return launch_k(k_xline<PI, PF, U, MODE, W, R>, (a.nunits + U - 1) / U, PI::G * U,
+                    sizeof(cpx<R>) * (XL * U + PI::N), s, a, done);
+}
+
+template <class P, int T, int MODE, int SP, int W, typename R>
+hipError_t launch_f3(const F3Args& a, hipStream_t s)
+{
+    static_assert(P::G * T <= 1024, "at most 1024 threads per block");
+    static_assert(tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::N <= 163840, "LDS per block exceeds 160 KiB");
+    static bool done = false;
+    return launch_k(k_f3<P, T, MODE, SP, W, R>, (a.Q + T - 1) / T, P::G * T,
+                    tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::N, s, a, done);
+}
+
+template <class V, class F>
+inline void add_variant(V* list, int& n, F fn, const char* name)
+{
+    if (n < NS_MAXV) list[n++] = V{fn, name};
+}
+
+// Per-size default schedule: each pass has its own line plan (threads per
+// line and radix order): the column passes (G, Rad), the x pass (GX, XRad
+// and its reverse XRadRev for the forward half) and the fused z pass (GF,
+// FRad); T / TF columns per block for the column and fused z passes and U
+// line pairs per block for the x pass, for FP32 and FP64.  Sizes that are
+// tuned add further variants in their translation unit.
 template <int N>
 struct SizeCfg;
 
@@ -359,45 +461,20 @@ struct Launch {
     static constexpr int U = f64 ? C::U64 : C::U32;
     static constexpr int SP = f64 ? C::SP64 : C::SP32;
     static constexpr int SPF = f64 ? C::SPF64 : C::SPF32;
-    static constexpr int XL = PX::lds_len > PXR::lds_len ? PX::lds_len : PXR::lds_len;
 
-    static hipError_t col_inv(const ColArgs& a, hipStream_t s)
-    {
-        static bool done = false;
-        return launch_k(k_colfft<P, T, +1, COL_INV_PAD, SP, R>, (a.Q + T - 1) / T, C::G * T,
-                        tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * N, s, a, done);
-    }
-    static hipError_t col_fwd(const ColArgs& a, hipStream_t s)
-    {
-        static bool done = false;
-        return launch_k(k_colfft<P, T, -1, COL_FWD_TRUNC, SP, R>, (a.Q + T - 1) / T, C::G * T,
-                        tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * N, s, a, done);
-    }
-    template <int MODE>
-    static hipError_t xl(const XArgs& a, hipStream_t s)
-    {
-        static bool done = false;
-        return launch_k(k_xline<PX, PXR, U, MODE, R>, (a.nunits + U - 1) / U, C::GX * U,
-                        sizeof(cpx<R>) * (XL * U + N), s, a, done);
-    }
-    template <int MODE>
-    static hipError_t f3(const F3Args& a, hipStream_t s)
-    {
-        static bool done = false;
-        return launch_k(k_f3<PF, TF, MODE, SPF, R>, (a.Q + TF - 1) / TF, C::GF * TF,
-                        tile_bytes<PF, TF, SPF, R>() + sizeof(cpx<R>) * N, s, a, done);
-    }
     static SizeKernels make()
     {
-        SizeKernels k;
+        SizeKernels k{};
         k.N = N;
-        k.col_inv = col_inv;
-        k.col_fwd = col_fwd;
-        k.x_rhs = xl<X_RHS>;
-        k.x_fwd3 = xl<X_FWD3>;
-        k.x_inv3 = xl<X_INV3>;
-        k.f3_rhs = f3<F3_RHS>;
-        k.f3_proj = f3<F3_PROJ>;
+        add_variant(k.inv, k.n_inv, launch_col<P, T, +1, COL_INV_PAD, SP, 1, R>, "default");
+        add_variant(k.fwd, k.n_fwd, launch_col<P, T, -1, COL_FWD_TRUNC, SP, 1, R>, "default");
+        add_variant(k.x, k.n_x, launch_x<PX, PXR, U, X_RHS, 1, R>, "default");
+        add_variant(k.f3, k.n_f3, launch_f3<PF, TF, F3_RHS, SPF, 1, R>, "default");
+        k.x_fwd3 = launch_x<PX, PXR, U, X_FWD3, 1, R>;
+        k.x_inv3 = launch_x<PX, PXR, U, X_INV3, 1, R>;
+        k.f3_proj = launch_f3<PF, TF, F3_PROJ, SPF, 1, R>;
+        k.x_adj = launch_x<PX, PXR, U, X_ADJ, 1, R>;
+        k.f3_adj = launch_f3<PF, TF, F3_ADJ, SPF, 1, R>;
         k.desc = C::desc;
         return k;
     }

@@ -10,6 +10,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -65,7 +67,37 @@ struct Group {
     void *A = nullptr, *Bw = nullptr, *C = nullptr;  // pass workspaces
     void *tw = nullptr, *rate = nullptr;
     double *dt = nullptr, *ones = nullptr;
+    // adjoint buffers (allocated on first use): stage u2, adjoint stages,
+    // strain, and 9-component pass workspaces
+    void *U2 = nullptr, *L1 = nullptr, *L2 = nullptr, *L3 = nullptr, *Sb = nullptr, *A9 = nullptr, *B9 = nullptr;
+    int sel[NS_NPASS] = {0, 0, 0, 0, 0};  // chosen schedule variant per pass
+    double tune_ms[NS_NPASS][NS_MAXV] = {};  // tuner timings (ms per launch), 0 = not timed
 };
+
+// variant count / name of pass p (I1 and I2 share the inverse column list)
+int variant_count(const SizeKernels* k, int p)
+{
+    switch (p) {
+        case 0:
+        case 1: return k->n_inv;
+        case 2: return k->n_x;
+        case 3: return k->n_fwd;
+        default: return k->n_f3;
+    }
+}
+
+const char* variant_name(const SizeKernels* k, int p, int v)
+{
+    switch (p) {
+        case 0:
+        case 1: return k->inv[v].name;
+        case 2: return k->x[v].name;
+        case 3: return k->fwd[v].name;
+        default: return k->f3[v].name;
+    }
+}
+
+const char* kPassName[NS_NPASS] = {"I1_inv_z", "I2_inv_y", "X_c2r_prod_r2c", "F2_fwd_y", "F3_fwd_z_epilogue"};
 
 }  // namespace
 
@@ -77,6 +109,8 @@ struct ns_ctx {
     size_t rsz = 4;  // bytes per real
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
+    std::vector<hipStream_t> branch;     // capture streams of groups 1.. (parallel graph branches)
+    std::vector<hipEvent_t> branch_ev;   // fork/join events for the capture
     std::vector<Group> groups;
     std::vector<void*> allocs;
     size_t bytes = 0;
@@ -84,6 +118,7 @@ struct ns_ctx {
     bool failed = false;
     hipGraphExec_t step_exec = nullptr;
     hipGraph_t step_graph = nullptr;
+    std::string tune_cache;
     double* edev = nullptr;  // energy check scratch
     // pass profiler: events bracketing each launch while enabled
     bool profile = false;
@@ -251,31 +286,55 @@ ns_status timed(ns_ctx* c, int pass, F&& launch)
     return NS_OK;
 }
 
-// One right-hand-side evaluation for every sample of a group, reading the
-// compact stage state us (and u0), writing out = ca u0 + cb us + cc dt F(us).
+// Arguments of the five passes of one right-hand-side evaluation for every
+// sample of a group: read the compact stage state us (and u0), write
+// out = ca u0 + cb us + cc dt F(us).
+struct PassArgs {
+    ColArgs i1, i2, f2;
+    XArgs x;
+    F3Args f3;
+};
+
+PassArgs pass_args(const Group& g, const void* us, void* out, const void* u0, double ca, double cb, double cc,
+                   const double* dt)
+{
+    const long long N = g.N, B = g.B, M = g.M, Mx = g.Mx, MMx = g.MMx;
+    PassArgs a;
+    // I1: [B][3][M][MMx] -> [B][3][N][MMx]
+    a.i1 = ColArgs{us, g.A, g.tw, B * 3 * MMx, MMx, 3, M * MMx, 3 * M * MMx, N * MMx, 3 * N * MMx, g.K, g.M, 1.0};
+    // I2: [B*3*N][M][Mx] -> [B*3*N][N][Mx]
+    a.i2 = ColArgs{g.A, g.Bw, g.tw, B * 3 * N * Mx, Mx, 3 * N, M * Mx, 3 * N * M * Mx, N * Mx, 3 * N * N * Mx,
+                   g.K, g.M, 1.0};
+    // X: [B][3][N*N][Mx] -> [B][6][N*N][Mx]
+    a.x = XArgs{g.Bw, g.C, g.tw, B * N * N / 2, N * N * Mx, N * N * Mx, 3 * N * N * Mx, 6 * N * N * Mx, g.K, 1.0 / N};
+    // F2: [B*6*N][N][Mx] -> [B*6*N][M][Mx]
+    a.f2 = ColArgs{g.C, g.A, g.tw, B * 6 * N * Mx, Mx, 6 * N, N * Mx, 6 * N * N * Mx, M * Mx, 6 * N * M * Mx,
+                   g.K, g.M, 1.0 / N};
+    // F3: [B][6][N][MMx] -> compact [B][3][M][MMx]
+    a.f3 = F3Args{g.A, u0, us, out, g.tw, g.rate, dt, B * MMx, (int)MMx, g.Mx, g.K, g.M,
+                  6 * N * MMx, N * MMx, g.st, M * MMx, ca, cb, cc, 1.0 / N, nullptr, nullptr, 0.0, 0.0};
+    return a;
+}
+
+hipError_t launch_pass(const Group& g, int p, int v, const PassArgs& a, hipStream_t s)
+{
+    const SizeKernels* k = g.kern;
+    switch (p) {
+        case 0: return k->inv[v].fn(a.i1, s);
+        case 1: return k->inv[v].fn(a.i2, s);
+        case 2: return k->x[v].fn(a.x, s);
+        case 3: return k->fwd[v].fn(a.f2, s);
+        default: return k->f3[v].fn(a.f3, s);
+    }
+}
+
 ns_status run_rhs(ns_ctx* c, Group& g, const void* us, void* out, const void* u0, double ca, double cb, double cc,
                   const double* dt)
 {
-    const SizeKernels* k = g.kern;
-    const long long N = g.N, B = g.B, M = g.M, Mx = g.Mx, MMx = g.MMx;
-    hipStream_t s = c->stream;
-    // I1: [B][3][M][MMx] -> [B][3][N][MMx]
+    const PassArgs a = pass_args(g, us, out, u0, ca, cb, cc, dt);
     ns_status st;
-    ColArgs a1{us, g.A, g.tw, B * 3 * MMx, MMx, M * MMx, N * MMx, g.K, g.M, 1.0};
-    if ((st = timed(c, 0, [&] { return k->col_inv(a1, s); }))) return st;
-    // I2: [B*3*N][M][Mx] -> [B*3*N][N][Mx]
-    ColArgs a2{g.A, g.Bw, g.tw, B * 3 * N * Mx, Mx, M * Mx, N * Mx, g.K, g.M, 1.0};
-    if ((st = timed(c, 1, [&] { return k->col_inv(a2, s); }))) return st;
-    // X: [B][3][N*N][Mx] -> [B][6][N*N][Mx]
-    XArgs ax{g.Bw, g.C, g.tw, B * N * N / 2, N * N * Mx, N * N * Mx, 3 * N * N * Mx, 6 * N * N * Mx, g.K, 1.0 / N};
-    if ((st = timed(c, 2, [&] { return k->x_rhs(ax, s); }))) return st;
-    // F2: [B*6*N][N][Mx] -> [B*6*N][M][Mx]
-    ColArgs a3{g.C, g.A, g.tw, B * 6 * N * Mx, Mx, N * Mx, M * Mx, g.K, g.M, 1.0 / N};
-    if ((st = timed(c, 3, [&] { return k->col_fwd(a3, s); }))) return st;
-    // F3: [B][6][N][MMx] -> compact [B][3][M][MMx]
-    F3Args f{g.A, u0, us, out, g.tw, g.rate, dt, B * MMx, (int)MMx, g.Mx, g.K, g.M,
-             6 * N * MMx, N * MMx, g.st, M * MMx, ca, cb, cc, 1.0 / N};
-    if ((st = timed(c, 4, [&] { return k->f3_rhs(f, s); }))) return st;
+    for (int p = 0; p < NS_NPASS; ++p)
+        if ((st = timed(c, p, [&] { return launch_pass(g, p, g.sel[p], a, c->stream); }))) return st;
     return NS_OK;
 }
 
@@ -348,10 +407,226 @@ ns_status set_dt(ns_ctx* c, const double* dt)
     return NS_OK;
 }
 
+// ---------------------------------------------------------------- adjoint
+ns_status ensure_adjoint_buffers(ns_ctx* c, Group& g)
+{
+    if (g.U2) return NS_OK;
+    const size_t cw = cwb(c);
+    const long long B = g.B, N = g.N;
+    ns_status st;
+    if ((st = dalloc(c, &g.U2, cw * g.st * B))) return st;
+    if ((st = dalloc(c, &g.L1, cw * g.st * B))) return st;
+    if ((st = dalloc(c, &g.L2, cw * g.st * B))) return st;
+    if ((st = dalloc(c, &g.L3, cw * g.st * B))) return st;
+    if ((st = dalloc(c, &g.Sb, cw * 2 * g.st * B))) return st;
+    if ((st = dalloc(c, &g.A9, cw * 9ULL * N * g.MMx * B))) return st;
+    if ((st = dalloc(c, &g.B9, cw * 9ULL * N * N * g.Mx * B))) return st;
+    return NS_OK;
+}
+
+// One vector-Jacobian product of the right-hand side for every sample of a
+// group, fused with an adjoint SSP-RK3 stage:
+//   out = c3 L3 + c2 L2 + c1 L1 + cc dt (F'(u)^T lam),
+//   F'(u)^T lam = T F[2 S(P lam) u] - eps |k|^{2s} Q lam,
+// u, lam, L1..L3 and out compact.
+ns_status run_vjp(ns_ctx* c, Group& g, const void* u, const void* lam, void* out, double c3, double c2, double c1,
+                  double cc, const double* dt)
+{
+    const SizeKernels* k = g.kern;
+    const long long N = g.N, B = g.B, M = g.M, Mx = g.Mx, MMx = g.MMx;
+    hipStream_t s = c->stream;
+    const size_t cw = cwb(c);
+    HIP_TRY(c, launch_strain(c->f64, lam, g.Sb, g.K, B, s));
+    // z: strain [B][6][M][MMx] and velocity [B][3][M][MMx] -> [B][9][N][MMx]
+    ColArgs s1{g.Sb, g.A9, g.tw, B * 6 * MMx, MMx, 6, M * MMx, 6 * M * MMx, N * MMx, 9 * N * MMx, g.K, g.M, 1.0};
+    HIP_TRY(c, k->inv[0].fn(s1, s));
+    ColArgs u1{u, (char*)g.A9 + cw * 6 * N * MMx, g.tw, B * 3 * MMx, MMx, 3, M * MMx, 3 * M * MMx, N * MMx,
+               9 * N * MMx, g.K, g.M, 1.0};
+    HIP_TRY(c, k->inv[0].fn(u1, s));
+    // y: [B][9N][M][Mx] -> [B][9N][N][Mx]
+    ColArgs y1{g.A9, g.B9, g.tw, B * 9 * N * Mx, Mx, 9 * N, M * Mx, 9 * N * M * Mx, N * Mx, 9 * N * N * Mx,
+               g.K, g.M, 1.0};
+    HIP_TRY(c, k->inv[0].fn(y1, s));
+    // x: a = 2 S u -> [B][3][N*N][Mx]
+    XArgs ax{g.B9, g.C, g.tw, B * N * N / 2, N * N * Mx, N * N * Mx, 9 * N * N * Mx, 3 * N * N * Mx, g.K, 1.0 / N};
+    HIP_TRY(c, k->x_adj(ax, s));
+    // y forward: [B][3N][N][Mx] -> [B][3N][M][Mx]
+    ColArgs y2{g.C, g.A, g.tw, B * 3 * N * Mx, Mx, 3 * N, N * Mx, 3 * N * N * Mx, M * Mx, 3 * N * M * Mx,
+               g.K, g.M, 1.0 / N};
+    HIP_TRY(c, k->fwd[0].fn(y2, s));
+    // z forward + adjoint stage epilogue
+    F3Args f{g.A, g.L3, lam, out, g.tw, g.rate, dt, B * MMx, (int)MMx, g.Mx, g.K, g.M,
+             3 * N * MMx, N * MMx, g.st, M * MMx, c3, 0.0, cc, 1.0 / N, g.L2, g.L1, c2, c1};
+    HIP_TRY(c, k->f3_adj(f, s));
+    return NS_OK;
+}
+
+// Adjoint of one SSP-RK3 step for a group: stage states u^n, u1, u2 in U0,
+// U1, U2; lambda_{n+1} in L3 on entry, lambda_n in L3 on return.
+ns_status adjoint_rk3(ns_ctx* c, Group& g)
+{
+    ns_status st;
+    // lambda_2 = 2/3 lambda_3 + 2/3 dt F'(u2)^T lambda_3
+    if ((st = run_vjp(c, g, g.U2, g.L3, g.L2, 2.0 / 3.0, 0.0, 0.0, 2.0 / 3.0, g.dt))) return st;
+    // lambda_1 = 1/4 lambda_2 + 1/4 dt F'(u1)^T lambda_2
+    if ((st = run_vjp(c, g, g.U1, g.L2, g.L1, 0.0, 0.25, 0.0, 0.25, g.dt))) return st;
+    // lambda_n = 1/3 lambda_3 + 3/4 lambda_2 + lambda_1 + dt F'(u^n)^T lambda_1
+    if ((st = run_vjp(c, g, g.U0, g.L1, g.L3, 1.0 / 3.0, 0.75, 1.0, 1.0, g.dt))) return st;
+    return NS_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+// Times every schedule variant of each pass on the group's own workspaces
+// (zero-filled) and keeps the fastest; results are cached per device, size,
+// precision and batch in a file of one JSON object per line.
+std::string tune_key(const ns_ctx* c, const Group& g)
+{
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "";
+    std::ostringstream o;
+    o << prop.gcnArchName << "/" << prop.multiProcessorCount << "CU/N=" << g.N << "/" << (c->f64 ? "f64" : "f32")
+      << "/B=" << g.B;
+    return o.str();
+}
+
+std::string json_field(const std::string& line, const char* name)
+{
+    const std::string key = std::string("\"") + name + "\":\"";
+    size_t a = line.find(key);
+    if (a == std::string::npos) return "";
+    a += key.size();
+    size_t b = line.find('"', a);
+    return b == std::string::npos ? "" : line.substr(a, b - a);
+}
+
+bool load_tuning(ns_ctx* c, Group& g, const std::string& path, const std::string& key)
+{
+    std::ifstream f(path);
+    if (!f) return false;
+    int found[NS_NPASS] = {-1, -1, -1, -1, -1};
+    std::string line;
+    while (std::getline(f, line)) {
+        if (json_field(line, "key") != key) continue;
+        const std::string pass = json_field(line, "pass"), var = json_field(line, "variant");
+        for (int p = 0; p < NS_NPASS; ++p) {
+            if (pass != kPassName[p]) continue;
+            for (int v = 0; v < variant_count(g.kern, p); ++v)
+                if (var == variant_name(g.kern, p, v)) found[p] = v;
+        }
+    }
+    for (int p = 0; p < NS_NPASS; ++p)
+        if (found[p] < 0) return false;
+    for (int p = 0; p < NS_NPASS; ++p) g.sel[p] = found[p];
+    (void)c;
+    return true;
+}
+
+void save_tuning(const Group& g, const std::string& path, const std::string& key)
+{
+    std::ofstream f(path, std::ios::app);
+    if (!f) return;
+    for (int p = 0; p < NS_NPASS; ++p) {
+        const int v = g.sel[p];
+        f << "{\"key\":\"" << key << "\",\"pass\":\"" << kPassName[p] << "\",\"variant\":\""
+          << variant_name(g.kern, p, v) << "\",\"ms\":" << g.tune_ms[p][v] << "}\n";
+    }
+}
+
+ns_status tune_group(ns_ctx* c, Group& g)
+{
+    const std::string key = tune_key(c, g);
+    const char* path = c->tune_cache.empty() ? nullptr : c->tune_cache.c_str();
+    if (path && !key.empty() && load_tuning(c, g, path, key)) return NS_OK;
+    const size_t cw = cwb(c);
+    HIP_TRY(c, hipMemsetAsync(g.U0, 0, cw * g.st * g.B, c->stream));
+    HIP_TRY(c, hipMemsetAsync(g.U1, 0, cw * g.st * g.B, c->stream));
+    HIP_TRY(c, hipMemsetAsync(g.A, 0, cw * 6ULL * g.N * g.MMx * g.B, c->stream));
+    HIP_TRY(c, hipMemsetAsync(g.Bw, 0, cw * 3ULL * g.N * g.N * g.Mx * g.B, c->stream));
+    HIP_TRY(c, hipMemsetAsync(g.C, 0, cw * 6ULL * g.N * g.N * g.Mx * g.B, c->stream));
+    const PassArgs a = pass_args(g, g.U0, g.U1, g.U0, 0.75, 0.25, 0.25, g.ones);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    ns_status st = NS_OK;
+    for (int p = 0; p < NS_NPASS && st == NS_OK; ++p) {
+        const int nv = variant_count(g.kern, p);
+        int best = 0;
+        double best_ms = 1e300;
+        for (int v = 0; v < nv && nv > 1; ++v) {
+            hipError_t e = launch_pass(g, p, v, a, c->stream);  // warm-up
+            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+            if (e == hipSuccess) e = launch_pass(g, p, v, a, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms1 = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms1, e0, e1);
+            // repeat short launches for a stable estimate (about 20 ms per variant)
+            int reps = ms1 > 0 ? (int)std::min(20.0, std::max(2.0, 20.0 / ms1)) : 2;
+            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_pass(g, p, v, a, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                st = fail(c, NS_ERR_HIP, "tuning pass %s variant %s failed: %s", kPassName[p],
+                          variant_name(g.kern, p, v), hipGetErrorString(e));
+                break;
+            }
+            g.tune_ms[p][v] = ms / reps;
+            if (g.tune_ms[p][v] < best_ms) {
+                best_ms = g.tune_ms[p][v];
+                best = v;
+            }
+        }
+        g.sel[p] = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == NS_OK && path && !key.empty()) save_tuning(g, path, key);
+    return st;
+}
+
+// One SSP-RK3 step of all groups captured as a graph: group 0 on the
+// capture stream, every further group on a branch stream forked from it and
+// joined back, so groups of different N run concurrently on replay.
+ns_status capture_step(ns_ctx* c)
+{
+    const size_t ng = c->groups.size();
+    hipStream_t main = c->cap_stream;
+    ns_status st = NS_OK;
+    if (ng > 1) {
+        HIP_TRY(c, hipEventRecord(c->branch_ev[0], main));
+        for (size_t g = 1; g < ng; ++g) HIP_TRY(c, hipStreamWaitEvent(c->branch[g - 1], c->branch_ev[0], 0));
+    }
+    for (size_t g = 0; g < ng && st == NS_OK; ++g) {
+        c->stream = g == 0 ? main : c->branch[g - 1];
+        st = rk3_step(c, c->groups[g]);
+    }
+    c->stream = main;
+    if (st) return st;
+    for (size_t g = 1; g < ng; ++g) {
+        HIP_TRY(c, hipEventRecord(c->branch_ev[g], c->branch[g - 1]));
+        HIP_TRY(c, hipStreamWaitEvent(main, c->branch_ev[g], 0));
+    }
+    return NS_OK;
+}
+
 ns_status ensure_graph(ns_ctx* c)
 {
     if (c->step_exec) return NS_OK;
     if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    while (c->branch.size() + 1 < c->groups.size()) {
+        hipStream_t b = nullptr;
+        HIP_TRY(c, hipStreamCreateWithFlags(&b, hipStreamNonBlocking));
+        c->branch.push_back(b);
+    }
+    while (c->branch_ev.size() < c->groups.size()) {
+        hipEvent_t e = nullptr;
+        HIP_TRY(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        c->branch_ev.push_back(e);
+    }
     hipStream_t user = c->stream;
     c->stream = c->cap_stream;
     hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
@@ -359,7 +634,7 @@ ns_status ensure_graph(ns_ctx* c)
         c->stream = user;
         return fail(c, NS_ERR_HIP, "hipStreamBeginCapture failed: %s", hipGetErrorString(e));
     }
-    ns_status st = step_all(c);
+    ns_status st = capture_step(c);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(c->cap_stream, &graph);
     c->stream = user;
@@ -406,6 +681,7 @@ ns_status ns_init(const ns_params* p, void* hip_stream, ns_ctx** out)
     c->prm = *p;
     c->prm.n = nullptr;
     c->prm.tune_cache = nullptr;
+    if (p->tune_cache) c->tune_cache = p->tune_cache;
     c->f64 = p->dtype == NS_F64;
     c->rsz = c->f64 ? 8 : 4;
     c->stream = (hipStream_t)hip_stream;
@@ -428,6 +704,9 @@ ns_status ns_init(const ns_params* p, void* hip_stream, ns_ctx** out)
     ns_status st = NS_OK;
     for (Group& g : c->groups)
         if ((st = setup_group(c, g))) break;
+    if (st == NS_OK && !(p->flags & NS_NO_TUNE))
+        for (Group& g : c->groups)
+            if ((st = tune_group(c, g))) break;
     if (st == NS_OK) st = dalloc(c, (void**)&c->edev, sizeof(double) * 4096);
     if (st != NS_OK) {
         g_init_error = c->err;
@@ -450,6 +729,8 @@ ns_status ns_destroy(ns_ctx* c)
     if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
     if (c->step_graph) (void)hipGraphDestroy(c->step_graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    for (hipStream_t b : c->branch) (void)hipStreamDestroy(b);
+    for (hipEvent_t e : c->branch_ev) (void)hipEventDestroy(e);
     for (void* p : c->allocs) (void)hipFree(p);
     delete c;
     return NS_OK;
@@ -468,6 +749,68 @@ ns_status ns_sync(ns_ctx* c)
 {
     CHECK_STATE(c);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return NS_OK;
+}
+
+static Group* group_of_size(ns_ctx* c, int n)
+{
+    for (Group& g : c->groups)
+        if (g.N == n) return &g;
+    return nullptr;
+}
+
+ns_status ns_variant_count(ns_ctx* c, int32_t n, int32_t pass, int32_t* count)
+{
+    CHECK_STATE(c);
+    Group* g = group_of_size(c, n);
+    if (!g || pass < 0 || pass >= NS_NPASS || !count) return fail(c, NS_ERR_ARG, "no samples of size %d or bad pass", n);
+    *count = variant_count(g->kern, pass);
+    return NS_OK;
+}
+
+ns_status ns_set_variant(ns_ctx* c, int32_t n, int32_t pass, int32_t variant)
+{
+    CHECK_STATE(c);
+    Group* g = group_of_size(c, n);
+    if (!g || pass < 0 || pass >= NS_NPASS) return fail(c, NS_ERR_ARG, "no samples of size %d or bad pass", n);
+    if (variant < 0 || variant >= variant_count(g->kern, pass))
+        return fail(c, NS_ERR_ARG, "variant %d out of range for pass %d at N=%d", variant, pass, n);
+    g->sel[pass] = variant;
+    if (c->step_exec) {  // the captured step used the old schedule
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        (void)hipGraphExecDestroy(c->step_exec);
+        (void)hipGraphDestroy(c->step_graph);
+        c->step_exec = nullptr;
+        c->step_graph = nullptr;
+    }
+    return NS_OK;
+}
+
+ns_status ns_tune_report(ns_ctx* c, char* buf, size_t len, size_t* needed)
+{
+    CHECK_STATE(c);
+    std::ostringstream o;
+    o << "[";
+    bool first = true;
+    for (const Group& g : c->groups) {
+        for (int p = 0; p < NS_NPASS; ++p) {
+            if (!first) o << ",";
+            first = false;
+            o << "{\"N\":" << g.N << ",\"batch\":" << g.B << ",\"pass\":\"" << kPassName[p] << "\",\"selected\":\""
+              << variant_name(g.kern, p, g.sel[p]) << "\",\"timings_ms\":{";
+            for (int v = 0; v < variant_count(g.kern, p); ++v)
+                o << (v ? "," : "") << "\"" << variant_name(g.kern, p, v) << "\":" << g.tune_ms[p][v];
+            o << "}}";
+        }
+    }
+    o << "]";
+    const std::string r = o.str();
+    if (needed) *needed = r.size() + 1;
+    if (buf && len > 0) {
+        const size_t m = std::min(len - 1, r.size());
+        memcpy(buf, r.data(), m);
+        buf[m] = 0;
+    }
     return NS_OK;
 }
 
@@ -524,11 +867,12 @@ ns_status ns_forward(ns_ctx* c, const void* const* u, void* const* uh)
         XArgs ax{u[i], g.C, g.tw, N * N / 2, N * N * N, N * N * Mx, 0, 0, g.K, 1.0 / N};
         HIP_TRY(c, g.kern->x_fwd3(ax, s));
         // y: [3N][N][Mx] -> [3N][M][Mx]
-        ColArgs a{g.C, g.A, g.tw, 3 * N * Mx, Mx, N * Mx, M * Mx, g.K, g.M, 1.0 / N};
-        HIP_TRY(c, g.kern->col_fwd(a, s));
+        ColArgs a{g.C, g.A, g.tw, 3 * N * Mx, Mx, 3 * N, N * Mx, 3 * N * N * Mx, M * Mx, 3 * N * M * Mx,
+                  g.K, g.M, 1.0 / N};
+        HIP_TRY(c, g.kern->fwd[0].fn(a, s));
         // z + T + Leray: [3][N][MMx] -> compact [3][M][MMx]
         F3Args f{g.A, nullptr, nullptr, g.U1, g.tw, g.rate, g.ones, MMx, (int)MMx, g.Mx, g.K, g.M,
-                 0, N * MMx, 0, M * MMx, 0.0, 0.0, 0.0, 1.0 / N};
+                 0, N * MMx, 0, M * MMx, 0.0, 0.0, 0.0, 1.0 / N, nullptr, nullptr, 0.0, 0.0};
         HIP_TRY(c, g.kern->f3_proj(f, s));
         HIP_TRY(c, launch_unpack(c->f64, g.U1, uh[i], g.N, g.K, s));
     }
@@ -545,10 +889,11 @@ ns_status ns_inverse(ns_ctx* c, const void* const* uh, void* const* u)
         const long long N = g.N, M = g.M, Mx = g.Mx, MMx = g.MMx;
         hipStream_t s = c->stream;
         HIP_TRY(c, launch_pack(c->f64, uh[i], g.U1, g.N, g.K, s));
-        ColArgs a1{g.U1, g.A, g.tw, 3 * MMx, MMx, M * MMx, N * MMx, g.K, g.M, 1.0};
-        HIP_TRY(c, g.kern->col_inv(a1, s));
-        ColArgs a2{g.A, g.Bw, g.tw, 3 * N * Mx, Mx, M * Mx, N * Mx, g.K, g.M, 1.0};
-        HIP_TRY(c, g.kern->col_inv(a2, s));
+        ColArgs a1{g.U1, g.A, g.tw, 3 * MMx, MMx, 3, M * MMx, 3 * M * MMx, N * MMx, 3 * N * MMx, g.K, g.M, 1.0};
+        HIP_TRY(c, g.kern->inv[0].fn(a1, s));
+        ColArgs a2{g.A, g.Bw, g.tw, 3 * N * Mx, Mx, 3 * N, M * Mx, 3 * N * M * Mx, N * Mx, 3 * N * N * Mx,
+                   g.K, g.M, 1.0};
+        HIP_TRY(c, g.kern->inv[0].fn(a2, s));
         XArgs ax{g.Bw, u[i], g.tw, N * N / 2, N * N * Mx, N * N * N, 0, 0, g.K, 1.0};
         HIP_TRY(c, g.kern->x_inv3(ax, s));
     }
@@ -609,16 +954,78 @@ ns_status ns_tape_bytes(const ns_ctx* c, int32_t nsteps, size_t* per)
     return NS_OK;
 }
 
-ns_status ns_step_taped(ns_ctx* c, void* const*, const double*, int32_t, void* const*)
+// tape layout per sample: [step][stage u^n, u1, u2][3][M][M][Mx] compact
+static size_t tape_step_bytes(const ns_ctx* c, const Group& g) { return (size_t)g.st * 2 * c->rsz * 3; }
+
+ns_status ns_step_taped(ns_ctx* c, void* const* uh, const double* dt, int32_t nsteps, void* const* tape)
 {
     CHECK_STATE(c);
-    return fail(c, NS_ERR_UNSUPPORTED, "ns_step_taped is not available in this build");
+    ns_status st;
+    if ((st = check_ptrs(c, (const void* const*)uh, "uhat")) || (st = check_ptrs(c, (const void* const*)tape, "tape")))
+        return st;
+    if ((st = check_dt(c, dt))) return st;
+    if (nsteps < 0) return fail(c, NS_ERR_ARG, "nsteps = %d must be >= 0", nsteps);
+    if (nsteps == 0) return NS_OK;
+    if ((st = pack_all(c, (const void* const*)uh, true))) return st;
+    if ((st = set_dt(c, dt))) return st;
+    const size_t sb = 2 * c->rsz;
+    for (int n = 0; n < nsteps; ++n) {
+        for (Group& g : c->groups) {
+            const size_t one = g.st * sb, step = tape_step_bytes(c, g);
+            auto save = [&](const void* src, int stage) -> ns_status {
+                for (int b = 0; b < g.B; ++b) {
+                    char* dst = (char*)tape[g.samples[b]] + (size_t)n * step + (size_t)stage * one;
+                    HIP_TRY(c, hipMemcpyAsync(dst, (const char*)src + b * one, one, hipMemcpyDeviceToDevice, c->stream));
+                }
+                return NS_OK;
+            };
+            if ((st = save(g.U0, 0))) return st;
+            if ((st = run_rhs(c, g, g.U0, g.U1, nullptr, 0.0, 1.0, 1.0, g.dt))) return st;
+            if ((st = save(g.U1, 1))) return st;
+            if ((st = run_rhs(c, g, g.U1, g.U1, g.U0, 0.75, 0.25, 0.25, g.dt))) return st;
+            if ((st = save(g.U1, 2))) return st;
+            if ((st = run_rhs(c, g, g.U1, g.U0, g.U0, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0, g.dt))) return st;
+        }
+    }
+    return unpack_all(c, uh, true);
 }
 
-ns_status ns_adjoint_step(ns_ctx* c, const void* const*, const void* const*, const double*, void* const*)
+ns_status ns_adjoint_step(ns_ctx* c, const void* const* uh, const void* const* tape_step, const double* dt,
+                          void* const* lam)
 {
     CHECK_STATE(c);
-    return fail(c, NS_ERR_UNSUPPORTED, "ns_adjoint_step is not available in this build");
+    ns_status st;
+    if ((st = check_ptrs(c, (const void* const*)lam, "lam")) || (st = check_dt(c, dt))) return st;
+    if (tape_step) {
+        if ((st = check_ptrs(c, tape_step, "tape_step"))) return st;
+    } else if ((st = check_ptrs(c, uh, "uhat_n"))) {
+        return st;
+    }
+    for (Group& g : c->groups)
+        if ((st = ensure_adjoint_buffers(c, g))) return st;
+    if ((st = set_dt(c, dt))) return st;
+    const size_t sb = 2 * c->rsz;
+    for (Group& g : c->groups) {
+        const size_t one = g.st * sb;
+        if (tape_step) {
+            void* dst[3] = {g.U0, g.U1, g.U2};
+            for (int b = 0; b < g.B; ++b)
+                for (int k = 0; k < 3; ++k)
+                    HIP_TRY(c, hipMemcpyAsync((char*)dst[k] + b * one, (const char*)tape_step[g.samples[b]] + k * one,
+                                              one, hipMemcpyDeviceToDevice, c->stream));
+        } else {
+            for (int b = 0; b < g.B; ++b)
+                HIP_TRY(c, launch_pack(c->f64, uh[g.samples[b]], (char*)g.U0 + b * one, g.N, g.K, c->stream));
+            if ((st = run_rhs(c, g, g.U0, g.U1, nullptr, 0.0, 1.0, 1.0, g.dt))) return st;
+            if ((st = run_rhs(c, g, g.U1, g.U2, g.U0, 0.75, 0.25, 0.25, g.dt))) return st;
+        }
+        for (int b = 0; b < g.B; ++b)
+            HIP_TRY(c, launch_pack(c->f64, lam[g.samples[b]], (char*)g.L3 + b * one, g.N, g.K, c->stream));
+        if ((st = adjoint_rk3(c, g))) return st;
+        for (int b = 0; b < g.B; ++b)
+            HIP_TRY(c, launch_unpack(c->f64, (const char*)g.L3 + b * one, lam[g.samples[b]], g.N, g.K, c->stream));
+    }
+    return NS_OK;
 }
 
 ns_status ns_energy_spectrum(ns_ctx* c, const void* const* uh, double* E, int32_t kbins)

@@ -1,11 +1,52 @@
-// Kernels for grid size N = 1024 (FP32 and FP64).
-#include "sizes.hpp"
+// Kernels for grid size N = 1024 (FP32 and FP64), with the schedule
+// variants the autotuner chooses from.
+#include "tuned.hpp"
 
 namespace ns {
+namespace {
+using PA = Plan<1024, 64, Radices<16, 16, 4>>;
+using PB = Plan<1024, 128, Radices<8, 8, 4, 4>>;
+using PBR = Plan<1024, 128, Radices<4, 4, 8, 8>>;
+using PC = Plan<1024, 64, Radices<16, 16, 4>>;
+using PCR = Plan<1024, 64, Radices<4, 16, 16>>;
+
+SizeKernels make32()
+{
+    using R = float;
+    SizeKernels k = Launch<1024, R>::make();  // col: PA T16 split; x: PB U2; f3: PB T4
+    add_col<PA, 8, 0, 1, R>(k, "G64 r16.16.4 T8");
+    add_col<PA, 16, 0, 1, R>(k, "G64 r16.16.4 T16");
+    add_col<PB, 8, 0, 1, R>(k, "G128 r8.8.4.4 T8");
+    add_col<PB, 8, 1, 1, R>(k, "G128 r8.8.4.4 T8 split");
+    add_x<PB, PBR, 2, 3, R>(k, "G128 r8.8.4.4 U2 w3");
+    add_x<PB, PBR, 1, 1, R>(k, "G128 r8.8.4.4 U1");
+    add_x<PB, PBR, 4, 1, R>(k, "G128 r8.8.4.4 U4");
+    add_x<PC, PCR, 2, 1, R>(k, "G64 r16.16.4 U2");
+    add_x<PC, PCR, 4, 1, R>(k, "G64 r16.16.4 U4");
+    add_f3<PB, 4, 1, 1, R>(k, "G128 r8.8.4.4 T4 split");
+    add_f3<PB, 2, 0, 1, R>(k, "G128 r8.8.4.4 T2");
+    add_f3<PB, 4, 0, 3, R>(k, "G128 r8.8.4.4 T4 w3");
+    add_f3<PC, 4, 0, 1, R>(k, "G64 r16.16.4 T4");
+    add_f3<PC, 8, 1, 1, R>(k, "G64 r16.16.4 T8 split");
+    return k;
+}
+
+SizeKernels make64()
+{
+    using R = double;
+    SizeKernels k = Launch<1024, R>::make();
+    add_col<PA, 8, 1, 1, R>(k, "G64 r16.16.4 T8 split");
+    add_col<PB, 4, 0, 1, R>(k, "G128 r8.8.4.4 T4");
+    add_x<PB, PBR, 2, 1, R>(k, "G128 r8.8.4.4 U2");
+    add_f3<PB, 2, 1, 1, R>(k, "G128 r8.8.4.4 T2 split");
+    return k;
+}
+}  // namespace
+
 const SizeKernels* kernels_1024(bool f64)
 {
-    static const SizeKernels k32 = Launch<1024, float>::make();
-    static const SizeKernels k64 = Launch<1024, double>::make();
+    static const SizeKernels k32 = make32();
+    static const SizeKernels k64 = make64();
     return f64 ? &k64 : &k32;
 }
 }  // namespace ns

@@ -1,0 +1,26 @@
+// Helpers to register extra schedule variants of the tuned passes.
+#pragma once
+#include "sizes.hpp"
+
+namespace ns {
+
+template <class P, int T, int SP, int W, typename R>
+void add_col(SizeKernels& k, const char* name)
+{
+    add_variant(k.inv, k.n_inv, launch_col<P, T, +1, COL_INV_PAD, SP, W, R>, name);
+    add_variant(k.fwd, k.n_fwd, launch_col<P, T, -1, COL_FWD_TRUNC, SP, W, R>, name);
+}
+
+template <class PI, class PF, int U, int W, typename R>
+void add_x(SizeKernels& k, const char* name)
+{
+    add_variant(k.x, k.n_x, launch_x<PI, PF, U, X_RHS, W, R>, name);
+}
+
+template <class P, int T, int SP, int W, typename R>
+void add_f3(SizeKernels& k, const char* name)
+{
+    add_variant(k.f3, k.n_f3, launch_f3<P, T, F3_RHS, SP, W, R>, name);
+}
+
+}  // namespace ns

@@ -23,7 +23,8 @@ NS_USE_GRAPH, NS_CHECK_FINITE, NS_NO_TUNE = 1, 2, 4
 # every symbol the header declares
 EXPORTS = ("ns_init", "ns_destroy", "ns_last_error", "ns_workspace_bytes", "ns_supported_sizes", "ns_forward",
            "ns_inverse", "ns_project", "ns_rhs", "ns_step", "ns_tape_bytes", "ns_step_taped", "ns_adjoint_step",
-           "ns_energy_spectrum", "ns_sync", "ns_profile", "ns_profile_read")
+           "ns_energy_spectrum", "ns_sync", "ns_profile", "ns_profile_read", "ns_variant_count", "ns_set_variant",
+           "ns_tune_report")
 NS_NPASS = 5
 PASS_NAMES = ("I1_inv_z", "I2_inv_y", "X_c2r_prod_r2c", "F2_fwd_y", "F3_fwd_z_epilogue")
 
@@ -71,6 +72,9 @@ def lib() -> ctypes.CDLL:
             "ns_sync": [P],
             "ns_profile": [P, I32],
             "ns_profile_read": [P, PD, ctypes.POINTER(ctypes.c_int64)],
+            "ns_variant_count": [P, I32, I32, ctypes.POINTER(I32)],
+            "ns_set_variant": [P, I32, I32, I32],
+            "ns_tune_report": [P, ctypes.c_char_p, S, ctypes.POINTER(S)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -105,7 +109,7 @@ class Solver:
     taking `uhat` accept a tensor (single sample) or a list of tensors."""
 
     def __init__(self, n, dtype=torch.float32, eps=-1.0, s=1.5, m_cut=-1.0, q_kind=0, theta=1.0,
-                 graph=True, check_finite=False, tune=False, stream=None, device=None):
+                 graph=True, check_finite=False, tune=False, tune_cache=None, stream=None, device=None):
         self.sizes = [int(n)] if isinstance(n, int) else [int(v) for v in n]
         if dtype not in (torch.float32, torch.float64):
             raise ValueError("dtype must be torch.float32 or torch.float64")
@@ -116,8 +120,9 @@ class Solver:
         self._L = lib()
         nn = (ctypes.c_int32 * len(self.sizes))(*self.sizes)
         flags = (NS_USE_GRAPH if graph else 0) | (NS_CHECK_FINITE if check_finite else 0) | (0 if tune else NS_NO_TUNE)
+        self._cache = tune_cache.encode() if tune_cache else None
         self._prm = _Params(NS_F32 if dtype == torch.float32 else NS_F64, len(self.sizes), nn, eps, s, m_cut,
-                            q_kind, theta, flags, None)
+                            q_kind, theta, flags, self._cache)
         self._nn = nn
         ctx = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -189,6 +194,48 @@ class Solver:
         self._check(self._L.ns_step(self._ctx, _ptrs(xs), arr, int(nsteps)))
         return uhat
 
+    def tape_step_bytes(self, n: int) -> int:
+        """Bytes of one step of the tape of a sample of size n: three compact
+        stage states [3][M][M][K+1] of complex numbers."""
+        K = (n - 1) // 3
+        cw = 8 if self.dtype == torch.float32 else 16
+        return 9 * (2 * K + 1) ** 2 * (K + 1) * cw
+
+    def new_tape(self, nsteps: int):
+        return [torch.empty(max(1, nsteps * self.tape_step_bytes(n)), dtype=torch.uint8, device=self.device)
+                for n in self.sizes]
+
+    def step_taped(self, uhat, dt, nsteps: int, tape):
+        xs = self._spec(self._list(uhat))
+        dts = [float(dt)] * len(xs) if not isinstance(dt, (list, tuple)) else [float(v) for v in dt]
+        arr = (ctypes.c_double * len(dts))(*dts)
+        tps = self._list(tape)
+        for t, n in zip(tps, self.sizes):
+            if t.device != self.device or t.numel() < nsteps * self.tape_step_bytes(n):
+                raise ValueError("tape too small")
+        self._check(self._L.ns_step_taped(self._ctx, _ptrs(xs), arr, int(nsteps), _ptrs(tps)))
+        return uhat
+
+    def adjoint_step(self, lam, dt, uhat_n=None, tape=None, step: int = 0):
+        """lam: dJ/du^{n+1} -> dJ/du^n in place.  Stage states from step
+        `step` of `tape` (from step_taped) or recomputed from uhat_n."""
+        ls = self._spec(self._list(lam))
+        dts = [float(dt)] * len(ls) if not isinstance(dt, (list, tuple)) else [float(v) for v in dt]
+        arr = (ctypes.c_double * len(dts))(*dts)
+        if tape is not None:
+            tps = self._list(tape)
+            tp = (ctypes.c_void_p * len(tps))()
+            for i, (t, n) in enumerate(zip(tps, self.sizes)):
+                off = step * self.tape_step_bytes(n)
+                if off + self.tape_step_bytes(n) > t.numel():
+                    raise ValueError("tape step out of range")
+                tp[i] = t.data_ptr() + off
+            self._check(self._L.ns_adjoint_step(self._ctx, None, tp, arr, _ptrs(ls)))
+        else:
+            us = self._spec(self._list(uhat_n))
+            self._check(self._L.ns_adjoint_step(self._ctx, _ptrs(us), None, arr, _ptrs(ls)))
+        return lam
+
     def spectrum(self, uhat, kbins: int):
         xs = self._spec(self._list(uhat))
         E = torch.zeros((len(xs), kbins), dtype=torch.float64, device=self.device)
@@ -204,6 +251,22 @@ class Solver:
         cnt = (ctypes.c_int64 * NS_NPASS)()
         self._check(self._L.ns_profile_read(self._ctx, ms, cnt))
         return {PASS_NAMES[p]: (ms[p], cnt[p]) for p in range(NS_NPASS)}
+
+    def variant_count(self, n: int, p: int) -> int:
+        c = ctypes.c_int32()
+        self._check(self._L.ns_variant_count(self._ctx, int(n), int(p), ctypes.byref(c)))
+        return c.value
+
+    def set_variant(self, n: int, p: int, v: int):
+        self._check(self._L.ns_set_variant(self._ctx, int(n), int(p), int(v)))
+
+    def tune_report(self):
+        import json
+        need = ctypes.c_size_t()
+        self._check(self._L.ns_tune_report(self._ctx, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(need.value)
+        self._check(self._L.ns_tune_report(self._ctx, buf, need.value, ctypes.byref(need)))
+        return json.loads(buf.value.decode())
 
     def workspace_bytes(self) -> int:
         v = ctypes.c_size_t()
@@ -223,3 +286,63 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class _Rollout(torch.autograd.Function):
+    """u0 (physical) -> u(T) (physical) after nsteps SSP-RK3 steps, with the
+    discrete adjoint in backward.  The forward keeps the state every
+    `ckpt_every` steps; the backward re-runs each segment from its
+    checkpoint with the stage states taped, then steps the adjoint back
+    through the tape.  The last segment is taped during the forward pass.
+
+    Gradient algebra: u(T) = F^-1[T u-hat(T)] and u-hat(0) = T P F[u0], with
+    F normalised by N^-3.  In the inner product Re sum_k conj(a_k) b_k the
+    adjoint of the first map is N^3 T F and of the second N^-3 F^-1 P T, so
+    with lambda(T) = T P F[g] (the solver's ns_forward) and the gradient
+    F^-1[P T lambda(0)] (ns_project then ns_inverse) the two factors cancel.
+    The projection added at the seed only removes a component that the
+    final projection removes anyway (the divergent part of lambda evolves
+    on its own)."""
+
+    @staticmethod
+    def forward(ctx, u0, solver, dt, nsteps, ckpt_every):
+        uh = solver.forward(u0.detach().contiguous())
+        ckpts = []
+        starts = list(range(0, nsteps, ckpt_every))
+        last_tape = None
+        for i, s0 in enumerate(starts):
+            length = min(ckpt_every, nsteps - s0)
+            ckpts.append((uh.clone(), length))
+            if i == len(starts) - 1:
+                last_tape = solver.new_tape(length)[0]
+                solver.step_taped(uh, dt, length, last_tape)
+            else:
+                solver.step(uh, dt, length)
+        ctx.solver, ctx.dt, ctx.ckpts, ctx.last_tape = solver, dt, ckpts, last_tape
+        return solver.inverse(uh)
+
+    @staticmethod
+    def backward(ctx, g):
+        S, dt = ctx.solver, ctx.dt
+        lam = S.forward(g.detach().contiguous().to(S.dtype))
+        for i in reversed(range(len(ctx.ckpts))):
+            uh0, length = ctx.ckpts[i]
+            if i == len(ctx.ckpts) - 1 and ctx.last_tape is not None:
+                tape = ctx.last_tape
+            else:
+                tape = S.new_tape(length)[0]
+                S.step_taped(uh0.clone(), dt, length, tape)
+            for j in reversed(range(length)):
+                S.adjoint_step(lam, dt, tape=tape, step=j)
+            del tape
+        ctx.last_tape = None
+        S.project(lam)
+        return S.inverse(lam), None, None, None, None
+
+
+def rollout(u0: torch.Tensor, solver: "Solver", dt: float, nsteps: int, ckpt_every: int = 20) -> torch.Tensor:
+    """Differentiable SSP-RK3 trajectory of a single-sample solver:
+    physical u0 [3,N,N,N] -> physical u(T) after nsteps steps of size dt."""
+    if len(solver.sizes) != 1:
+        raise ValueError("rollout needs a single-sample solver")
+    return _Rollout.apply(u0, solver, float(dt), int(nsteps), int(ckpt_every))

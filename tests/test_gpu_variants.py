@@ -1,0 +1,98 @@
+"""Every schedule variant the autotuner can pick computes the same
+right-hand side: each pass's variants are forced one at a time (the other
+passes at their default) and checked against the oracle, by the full
+pseudo-spectral oracle at 64^3/128^3 and by the sparse Galerkin oracle at
+256^3 (FP64) and 512^3/1024^3 (FP32)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2401_09843_amd import inputs
+
+pytestmark = pytest.mark.gpu
+NPASS = 5
+
+
+@pytest.fixture(scope="module")
+def ns():
+    from paper_2401_09843_amd import ns as m
+    assert torch.cuda.is_available()
+    m.lib()
+    return m
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def each_variant(S, n):
+    for p in range(NPASS):
+        for v in range(S.variant_count(n, p)):
+            S.set_variant(n, p, v)
+            yield p, v
+        S.set_variant(n, p, 0)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("n", [64, 128])
+def test_variants_small(ns, orc, n, dtype):
+    uh = inputs.half_spectrum(inputs.random_field(n, seed=3000 + n))
+    ref = orc.rhs(uh, n)
+    cd = torch.complex128 if dtype == torch.float64 else torch.complex64
+    S = ns.Solver(n, dtype=dtype, graph=False)
+    x = torch.from_numpy(uh).to(cd).cuda()
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    for p, v in each_variant(S, n):
+        print("n=%d %s pass %d variant %d" % (n, dtype, p, v), flush=True)
+        got = S.rhs(x).cpu().numpy().astype(np.complex128)
+        assert rel(got, ref) <= tol, (p, v)
+
+
+def _support(modes, K):
+    s = set()
+    for p in modes:
+        for q in modes:
+            k = p + q
+            if k[0] >= 0 and np.all(np.abs(k) <= K):
+                s.add(tuple(int(v) for v in k))
+        if p[0] >= 0:
+            s.add(tuple(int(v) for v in p))
+    return np.array(sorted(s), dtype=np.int64)
+
+
+@pytest.mark.parametrize("n,dtype,tol", [(256, torch.float64, 1e-12), (512, torch.float32, 1e-5),
+                                         (1024, torch.float32, 1e-5)])
+def test_variants_full_size(ns, orc, n, dtype, tol):
+    modes, coefs = inputs.sparse_modes(n, seed=n + 11, count=16)
+    kout = _support(modes, (n - 1) // 3)
+    ref = orc.rhs_sparse(modes, coefs, kout, n, orc.Params())
+    cd = torch.complex128 if dtype == torch.float64 else torch.complex64
+    S = ns.Solver(n, dtype=dtype, graph=False)
+    uh = torch.zeros((3, n, n, n // 2 + 1), dtype=cd, device="cuda")
+    sel = modes[:, 0] >= 0
+    for c in range(3):
+        uh[c, torch.as_tensor(modes[sel, 2] % n), torch.as_tensor(modes[sel, 1] % n),
+           torch.as_tensor(modes[sel, 0])] = torch.as_tensor(coefs[sel, c]).to(cd).cuda()
+    oz, oy, ox = (torch.as_tensor(kout[:, 2] % n), torch.as_tensor(kout[:, 1] % n), torch.as_tensor(kout[:, 0]))
+    for p, v in each_variant(S, n):
+        print("n=%d pass %d variant %d" % (n, p, v), flush=True)
+        F = S.rhs(uh)
+        got = torch.stack([F[c, oz, oy, ox] for c in range(3)], dim=1).cpu().numpy().astype(np.complex128)
+        total = float(torch.sum(torch.abs(F.to(torch.complex128)) ** 2).item())
+        del F
+        assert rel(got, ref) <= tol, (p, v)
+        assert max(total - float(np.sum(np.abs(got) ** 2)), 0.0) <= 10 * tol ** 2 * total, (p, v)
+
+
+def test_tuner_picks_a_listed_variant_and_caches(ns, tmp_path):
+    n = 64
+    path = str(tmp_path / "tune.jsonl")
+    S = ns.Solver(n, dtype=torch.float32, tune=True, tune_cache=path)
+    rep = S.tune_report()
+    assert len(rep) == NPASS
+    for r in rep:
+        assert r["selected"] in r["timings_ms"]
+    lines = open(path).read().strip().splitlines()
+    assert len(lines) == NPASS
+    S2 = ns.Solver(n, dtype=torch.float32, tune=True, tune_cache=path)  # read back
+    assert [r["selected"] for r in S2.tune_report()] == [r["selected"] for r in rep]

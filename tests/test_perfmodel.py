@@ -1,0 +1,51 @@
+"""The byte-counting model: the paper's lower-bound formulas reproduce its
+Table 2, and the pass model counts the bytes of the pruned passes."""
+import os
+
+import pytest
+
+from paper_2401_09843_amd import perfmodel as pm
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table2_lower_bounds.txt")
+
+
+def golden():
+    out = {}
+    for line in open(GOLDEN):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()
+            out[k] = float(v)
+    return out
+
+
+def test_reproduces_table2():
+    g = golden()
+    N, p, s = 512, 8, 4
+    bD, bHD = 488.64e9, 19.24e9
+    got = {
+        "padding": pm.t_pad(N, p, s, bD),
+        "unpadding": pm.t_unpad(N, p, s, bD),
+        "transpose_u": 3 * pm.t_transpose(N, p, s, bD, bHD, 9e9),
+        "transpose_B": 6 * pm.t_transpose(N, p, s, bD, bHD, 9e9),
+        "transpose_u_alltoall": 3 * pm.t_transpose(N, p, s, bD, bHD, 4e9),
+        "transpose_B_alltoall": 6 * pm.t_transpose(N, p, s, bD, bHD, 4e9),
+    }
+    for k, v in g.items():
+        assert got[k] * 1e3 == pytest.approx(v, abs=6e-4), k
+
+
+def test_pass_model_hand_count():
+    # N = 8: K = 2, M = 5, Mx = 3
+    c = pm.pass_cw(8, 2)
+    assert c["I1_inv_z"] == 3 * 25 * 3 + 3 * 8 * 5 * 3
+    assert c["I2_inv_y"] == 3 * 8 * 5 * 3 + 3 * 64 * 3
+    assert c["X_c2r_prod_r2c"] == 9 * 64 * 3
+    assert c["F2_fwd_y"] == 6 * 64 * 3 + 6 * 8 * 5 * 3
+    assert c["F3_fwd_z_epilogue"] == 6 * 8 * 5 * 3 + 9 * 75
+    assert pm.pass_cw(8, 1)["F3_fwd_z_epilogue"] == 6 * 8 * 5 * 3 + 6 * 75
+
+
+def test_step_bytes_1024():
+    b = pm.step_bytes(1024, 4)
+    assert 299e9 < b < 301e9  # about 34.97 N^3 complex words
+    assert b / (8 * 1024 ** 3) == pytest.approx(34.97, abs=0.01)
