@@ -59,7 +59,7 @@ def run_ensemble(args):
         fields.append(u)
         dts.append(float(0.5 * (2 * 3.141592653589793 / n) / u.abs().sum(0).max().item()))
     print("ensemble: %d samples, %d steps" % (len(sizes), steps), file=sys.stderr, flush=True)
-    E = ns.Solver(sizes, dtype=torch.float32, graph=True, tune=not args.no_tune)
+    E = ns.Solver(sizes, dtype=torch.float32, graph=True, tune=not args.no_tune, tune_cache=args.tune_cache)
     uhs = E.forward(fields)
     init = [t.clone() for t in uhs]
     E.step(uhs, dts, args.warmup)
@@ -71,7 +71,8 @@ def run_ensemble(args):
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
     # looping the plain solver (one context per grid size, one sample at a time)
-    plain = {n: ns.Solver(n, dtype=torch.float32, graph=True, tune=not args.no_tune) for n in sorted(set(sizes))}
+    plain = {n: ns.Solver(n, dtype=torch.float32, graph=True, tune=not args.no_tune, tune_cache=args.tune_cache)
+             for n in sorted(set(sizes))}
     loop = [t.clone() for t in init]
     for i, n in enumerate(sizes[:2]):
         plain[n].step(init[i].clone(), dts[i], args.warmup)
@@ -113,13 +114,31 @@ def run_ensemble(args):
     print(json.dumps(out))
 
 
+def kernel_source_hash() -> str:
+    """SHA-256 of the HIP sources; PMC traffic figures are valid only for
+    the kernels they were measured on."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2401_09843_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode())
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel: str, n: int):
-    """HBM bytes per launch from committed rocprofv3 PMC summaries, if any."""
+    """HBM bytes per launch of a pass from the committed rocprofv3 PMC
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel
+    calibration), or None if there is none or the kernels changed since."""
     path = os.path.join(PROFILE_DIR, "traffic_%s_n%d.json" % (kernel, n))
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
+    if d.get("source_hash") != kernel_source_hash():
+        return None
     return d.get("bytes_per_launch")
 
 
@@ -133,10 +152,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the built-in schedules instead of the autotuner")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (JSON lines) to read or append")
+    ap.add_argument("--print-source-hash", action="store_true")
     ap.add_argument("--ensemble", action="store_true", help="run the 96-sample ensemble workload instead")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 2 GiB three times (PMC byte-counter calibration)")
     args = ap.parse_args()
+    if args.print_source_hash:
+        print(kernel_source_hash())
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
               file=sys.stderr)
@@ -166,7 +190,7 @@ def main():
     torch.cuda.set_device(dev)
     print("bench: n=%d %s steps=%d warmup=%d" % (n, args.dtype, args.steps, args.warmup), file=sys.stderr, flush=True)
 
-    S = ns.Solver(n, dtype=dt_torch, graph=True, tune=not args.no_tune)
+    S = ns.Solver(n, dtype=dt_torch, graph=True, tune=not args.no_tune, tune_cache=args.tune_cache)
     schedule = {r["pass"]: r["selected"] for r in S.tune_report()}
     print("bench: schedule %s" % json.dumps(S.tune_report()), file=sys.stderr, flush=True)
     u0, _, _ = inputs.shear_layer_torch(n, seed=0, device=dev, dtype=dt_torch)

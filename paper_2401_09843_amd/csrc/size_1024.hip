@@ -9,6 +9,8 @@ using PB = Plan<1024, 128, Radices<8, 8, 4, 4>>;
 using PBR = Plan<1024, 128, Radices<4, 4, 8, 8>>;
 using PC = Plan<1024, 64, Radices<16, 16, 4>>;
 using PCR = Plan<1024, 64, Radices<4, 16, 16>>;
+using PD = Plan<1024, 256, Radices<4, 4, 4, 4, 4>>;
+using PE = Plan<1024, 128, Radices<4, 8, 8, 4>>;
 
 SizeKernels make32()
 {
@@ -23,11 +25,15 @@ SizeKernels make32()
     add_x<PB, PBR, 4, 1, R>(k, "G128 r8.8.4.4 U4");
     add_x<PC, PCR, 2, 1, R>(k, "G64 r16.16.4 U2");
     add_x<PC, PCR, 4, 1, R>(k, "G64 r16.16.4 U4");
+    add_x<PD, PD, 1, 1, R>(k, "G256 r4.4.4.4.4 U1");
+    add_x<PE, PE, 2, 1, R>(k, "G128 r4.8.8.4 U2");
     add_f3<PB, 4, 1, 1, R>(k, "G128 r8.8.4.4 T4 split");
     add_f3<PB, 2, 0, 1, R>(k, "G128 r8.8.4.4 T2");
     add_f3<PB, 4, 0, 3, R>(k, "G128 r8.8.4.4 T4 w3");
     add_f3<PC, 4, 0, 1, R>(k, "G64 r16.16.4 T4");
     add_f3<PC, 8, 1, 1, R>(k, "G64 r16.16.4 T8 split");
+    add_f3<PD, 4, 0, 1, R>(k, "G256 r4.4.4.4.4 T4");
+    add_f3<PD, 2, 0, 1, R>(k, "G256 r4.4.4.4.4 T2");
     return k;
 }
 
