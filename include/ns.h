@@ -147,7 +147,9 @@ ns_status ns_step_taped(ns_ctx* ctx, void* const* uhat_inout, const double* dt, 
  * spectrum of conj(a_k) b_k).  lam (R2C layout) holds dJ/du^{n+1} on entry
  * and dJ/du^n on return.  The stage states come from tape_step[i] (one step
  * of a tape written by ns_step_taped, i.e. tape + step * per_step_bytes) or,
- * if tape_step is NULL, are recomputed from uhat_n (the step's input). */
+ * if tape_step is NULL, are recomputed from uhat_n (the step's input).
+ * As for every entry point, modes of lam outside the 2/3 cube are ignored
+ * (the step maps them to zero, so their adjoint is zero) and written as 0. */
 ns_status ns_adjoint_step(ns_ctx* ctx, const void* const* uhat_n, const void* const* tape_step,
                           const double* dt, void* const* lam_inout);
 

@@ -433,6 +433,85 @@ hipError_t launch_f3(const F3Args& a, hipStream_t s)
                     tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::N, s, a, done);
 }
 
+// Epilogue of the split F3 schedule: the six truncated, scaled components
+// B-hat (compact, [B][6][M][MMx] in a.scratch) -> b = -i sum_j k_j B_ij,
+// Leray projection, hyperviscosity and the SSP-RK3 stage combination, one
+// thread per retained mode.
+template <typename R>
+__global__ void __launch_bounds__(256) k_f3_epilogue(F3Args a)
+{
+    const long long per = (long long)a.M * a.MMx;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long B = a.Q / a.MMx;
+    if (idx >= B * per) return;
+    const long long samp = idx / per, m = idx % per;
+    const int jz = (int)(m / a.MMx), s = (int)(m % a.MMx);
+    const int K = a.K, M = a.M;
+    const int jy = s / a.Mx, kxi = s % a.Mx;
+    const int kyi = jy <= K ? jy : jy - M, kzi = jz <= K ? jz : jz - M;
+    const R kv[3] = {(R)kxi, (R)kyi, (R)kzi};
+    const cpx<R>* Bh = static_cast<const cpx<R>*>(a.scratch) + samp * 6 * per + m;
+    cpx<R> Bv[6];
+#pragma unroll
+    for (int p = 0; p < 6; ++p) Bv[p] = Bh[p * per];
+    // b_i = -i sum_j k_j B_ij over the upper-triangle storage
+    const int tri[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+    cpx<R> b[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        R sx = 0, sy = 0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            sx += kv[j] * Bv[tri[i][j]].x;
+            sy += kv[j] * Bv[tri[i][j]].y;
+        }
+        b[i] = {sy, -sx};
+    }
+    const int k2 = kxi * kxi + kyi * kyi + kzi * kzi;
+    if (k2 > 0) {
+        const R inv = (R)1 / (R)k2;
+        const R bx = (kv[0] * b[0].x + kv[1] * b[1].x + kv[2] * b[2].x) * inv;
+        const R by = (kv[0] * b[0].y + kv[1] * b[1].y + kv[2] * b[2].y) * inv;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            b[j].x -= kv[j] * bx;
+            b[j].y -= kv[j] * by;
+        }
+    }
+    const R rt = static_cast<const R*>(a.rate)[k2];
+    const R ca = (R)a.ca, cb = (R)a.cb, cdt = (R)(a.cc * a.dt[samp]);
+    const long long st = samp * a.st_ss + (long long)jz * a.MMx + s;
+    const cpx<R>* us = static_cast<const cpx<R>*>(a.us) + st;
+    const cpx<R>* u0 = static_cast<const cpx<R>*>(a.u0) + st;
+    cpx<R>* o = static_cast<cpx<R>*>(a.out) + st;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const cpx<R> w = us[j * a.st_cs];
+        const cpx<R> f = {b[j].x - rt * w.x, b[j].y - rt * w.y};
+        cpx<R> r = {cb * w.x + cdt * f.x, cb * w.y + cdt * f.y};
+        if (a.ca != 0.0) {
+            const cpx<R> w0 = u0[j * a.st_cs];
+            r.x += ca * w0.x;
+            r.y += ca * w0.y;
+        }
+        o[j * a.st_cs] = r;
+    }
+}
+
+// Split F3 schedule: forward z of the six components with truncation into
+// scratch (a column pass), then the pointwise epilogue.
+template <class P, int T, int SP, int W, typename R>
+hipError_t launch_f3_split(const F3Args& a, hipStream_t s)
+{
+    const long long B = a.Q / a.MMx, MM = (long long)a.M * a.MMx;
+    ColArgs c{a.in, a.scratch, a.tw, a.Q * 6, a.MMx, 6, a.in_cs, a.in_ss, MM, 6 * MM, a.K, a.M, a.scale};
+    hipError_t e = launch_col<P, T, -1, COL_FWD_TRUNC, SP, W, R>(c, s);
+    if (e != hipSuccess) return e;
+    const long long total = B * MM;
+    hipLaunchKernelGGL(k_f3_epilogue<R>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 template <class V, class F>
 inline void add_variant(V* list, int& n, F fn, const char* name)
 {

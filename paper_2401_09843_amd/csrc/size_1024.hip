@@ -34,6 +34,7 @@ SizeKernels make32()
     add_f3<PC, 8, 1, 1, R>(k, "G64 r16.16.4 T8 split");
     add_f3<PD, 4, 0, 1, R>(k, "G256 r4.4.4.4.4 T4");
     add_f3<PD, 2, 0, 1, R>(k, "G256 r4.4.4.4.4 T2");
+    add_f3_split<PA, 16, 1, 1, R>(k, "split: G64 r16.16.4 T16 split + epilogue");
     return k;
 }
 
