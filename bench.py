@@ -24,7 +24,7 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 
 
-def cpu_baseline(n_sample: int = 128):
+def cpu_baseline(n_sample: int = 256):
     """The oracle (FP64, all host cores) for one SSP-RK3 step of the same
     shear-layer family at n_sample^3; returns Mpts*RK-steps/s."""
     from oracle import oracle as orc
