@@ -71,8 +71,12 @@ def run_ensemble(args):
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
     # looping the plain solver (one context per grid size, one sample at a time)
-    plain = {n: ns.Solver(n, dtype=torch.float32, graph=True, tune=not args.no_tune, tune_cache=args.tune_cache)
-             for n in sorted(set(sizes))}
+    # with the schedules the ensemble runs, so that both compute the same bits
+    plain = {n: ns.Solver(n, dtype=torch.float32, graph=True, tune=False) for n in sorted(set(sizes))}
+    passes = ["I1_inv_z", "I2_inv_y", "X_c2r_prod_r2c", "F2_fwd_y", "F3_fwd_z_epilogue"]
+    for r in E.tune_report():
+        names = list(r["timings_ms"].keys())
+        plain[r["N"]].set_variant(r["N"], passes.index(r["pass"]), names.index(r["selected"]))
     loop = [t.clone() for t in init]
     for i, n in enumerate(sizes[:2]):
         plain[n].step(init[i].clone(), dts[i], args.warmup)

@@ -153,6 +153,13 @@ ns_status ns_step_taped(ns_ctx* ctx, void* const* uhat_inout, const double* dt, 
 ns_status ns_adjoint_step(ns_ctx* ctx, const void* const* uhat_n, const void* const* tape_step,
                           const double* dt, void* const* lam_inout);
 
+/* nsteps adjoint steps backward through a whole tape written by
+ * ns_step_taped(nsteps): lam holds dJ/du at the end of the taped steps on
+ * entry and dJ/du at their start on return (steps nsteps-1 .. 0; lam stays
+ * in the compact layout in between). */
+ns_status ns_adjoint_steps(ns_ctx* ctx, const void* const* tape, int32_t nsteps, const double* dt,
+                           void* const* lam_inout);
+
 /* Energy spectrum (the energy-spectrum writer of Sec. 2.4):
  * E[i][kappa] = 1/2 sum over modes of the full spectrum with
  * round(|k|) = kappa of |u-hat_k|^2, kappa = 0..kbins-1, written as FP64

@@ -11,8 +11,9 @@
 // ((b - k) R_s + k) + m P_s, k = b mod P_s (Stockham autosort order).  After
 // the last stage thread t holds X[t + q G + m N/R_last] in v[q R_last + m],
 // i.e. outputs are in natural order with no bit reversal.  Twiddles come from
-// a table tw[e] = exp(-2 pi i e / N) rounded from extended precision on the
-// host; the inverse direction uses its conjugate.
+// a table exp(-2 pi i e / N) rounded from extended precision on the host,
+// regrouped per stage in LDS (TwTable); the inverse direction uses the
+// conjugate.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -200,14 +201,6 @@ __device__ __forceinline__ long long xcd_tile(long long nb)
     return x * c + (x < rem ? x : rem) + j;
 }
 
-// Copy the N-entry twiddle table to LDS (all threads of the block take part).
-template <typename T>
-__device__ __forceinline__ void load_twiddles(cpx<T>* dst, const cpx<T>* __restrict__ src, int n)
-{
-    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
-    __syncthreads();
-}
-
 // ---------------------------------------------------------------- plans
 template <int... Rs>
 struct Radices;
@@ -237,11 +230,11 @@ __device__ __forceinline__ int lds_pos(int pos) { return pos + pos / PD; }
 // element pos lives at lds[lds_pos<PD>(pos) * LS].  With SP = 1 the
 // exchange moves the real and then the imaginary parts through a real-valued
 // buffer of the same layout (half the LDS, twice the barriers).
-template <int N, int G, int DIR, int PD, int LS, int SP, typename T, int P, int... Rs>
+template <int N, int G, int DIR, int PD, int LS, int SP, typename T, int P, int OFF, int... Rs>
 struct Stages;
 
-template <int N, int G, int DIR, int PD, int LS, int SP, typename T, int P, int R, int... Rest>
-struct Stages<N, G, DIR, PD, LS, SP, T, P, R, Rest...> {
+template <int N, int G, int DIR, int PD, int LS, int SP, typename T, int P, int OFF, int R, int... Rest>
+struct Stages<N, G, DIR, PD, LS, SP, T, P, OFF, R, Rest...> {
     static constexpr int E = N / G;
     static constexpr int NB = N / (R * G);
     static_assert(NB * R * G == N, "G must divide N / R for every radix");
@@ -274,7 +267,7 @@ struct Stages<N, G, DIR, PD, LS, SP, T, P, R, Rest...> {
             if constexpr (P > 1) {
                 const int k = b % P;
 #pragma unroll
-                for (int m = 1; m < R; ++m) v[q * R + m] = twiddle<DIR>(v[q * R + m], tw[m * k * (N / (P * R))]);
+                for (int m = 1; m < R; ++m) v[q * R + m] = twiddle<DIR>(v[q * R + m], tw[OFF + (m - 1) * P + k]);
             }
             Dft<R, DIR, T>::run(&v[q * R]);
         }
@@ -287,7 +280,33 @@ struct Stages<N, G, DIR, PD, LS, SP, T, P, R, Rest...> {
                 exchange<R2>(v, t, l, [](cpx<T> a) { return a.x; }, [](cpx<T>& d, T a) { d.x = a; });
                 exchange<R2>(v, t, l, [](cpx<T> a) { return a.y; }, [](cpx<T>& d, T a) { d.y = a; });
             }
-            Stages<N, G, DIR, PD, LS, SP, T, P * R, Rest...>::run(v, t, lds, tw);
+            Stages<N, G, DIR, PD, LS, SP, T, P * R, OFF + (P > 1 ? (R - 1) * P : 0), Rest...>::run(v, t, lds, tw);
+        }
+    }
+};
+
+// Per-stage twiddle tables in LDS: stage s with span P > 1 and radix R keeps
+// w_{PR}^{m k} at [(m-1) P + k] (m = 1..R-1, k < P), so lanes with
+// consecutive k read consecutive words and lanes with equal k broadcast.
+template <int N, int P, int... Rs>
+struct TwTable {
+    static constexpr int len = 0;
+    template <typename T>
+    __device__ __forceinline__ static void fill(int, cpx<T>*, const cpx<T>* __restrict__) {}
+};
+
+template <int N, int P, int R, int... Rest>
+struct TwTable<N, P, R, Rest...> {
+    static constexpr int here = P > 1 ? (R - 1) * P : 0;
+    static constexpr int len = here + TwTable<N, P * R, Rest...>::len;
+    template <typename T>
+    __device__ __forceinline__ static void fill(int idx, cpx<T>* dst, const cpx<T>* __restrict__ src)
+    {
+        if (idx < here) {
+            const int m = idx / P + 1, k = idx % P;
+            dst[idx] = src[m * k * (N / (P * R))];
+        } else {
+            TwTable<N, P * R, Rest...>::fill(idx - here, dst + here, src);
         }
     }
 };
@@ -303,11 +322,22 @@ struct Plan<N_, G_, Radices<Rs...>> {
     static_assert(Rad::product == N_, "radices must multiply to N");
     // LDS elements per line (with padding)
     static constexpr int lds_len = N_ + N_ / R0 + 1;
+    // entries of the per-stage twiddle tables (at most N)
+    static constexpr int tw_len = TwTable<N_, 1, Rs...>::len;
+
+    // build the stage tables in LDS from the N-entry table exp(-2 pi i e/N)
+    // (all threads of the block take part)
+    template <typename T>
+    __device__ __forceinline__ static void load_tw(cpx<T>* dst, const cpx<T>* __restrict__ src)
+    {
+        for (int i = threadIdx.x; i < tw_len; i += blockDim.x) TwTable<N_, 1, Rs...>::fill(i, dst, src);
+        __syncthreads();
+    }
 
     template <int DIR, int LS, int SP = 0, typename T>
     __device__ __forceinline__ static void run(cpx<T> (&v)[E], int t, cpx<T>* lds, const cpx<T>* __restrict__ tw)
     {
-        Stages<N_, G_, DIR, R0, LS, SP, T, 1, Rs...>::run(v, t, lds, tw);
+        Stages<N_, G_, DIR, R0, LS, SP, T, 1, 0, Rs...>::run(v, t, lds, tw);
     }
     // position of register element i = q * R + m at stage-0 input / final output
     __device__ __forceinline__ static constexpr int in_pos(int t, int i) { return t + (i / R0) * G + (i % R0) * (N / R0); }

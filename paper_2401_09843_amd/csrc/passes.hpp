@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(P::G* T, W) k_colfft(ColArgs a)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     cpx<R>* twl = reinterpret_cast<cpx<R>*>(smem_raw + tile_bytes<P, T, SP, R>());
-    load_twiddles(twl, static_cast<const cpx<R>*>(a.tw), N);
+    P::template load_tw<R>(twl, static_cast<const cpx<R>*>(a.tw));
     const int tid = threadIdx.x, c = tid % T, g = tid / T;
     const long long q = xcd_tile(gridDim.x) * T + c;
     const bool valid = q < a.Q;
@@ -76,6 +76,72 @@ __global__ void __launch_bounds__(P::G* T, W) k_colfft(ColArgs a)
     }
 }
 
+// Persistent form: a fixed grid, each block walks a share of its XCD's
+// contiguous tile range and loads the next tile into registers while it
+// transforms the current one.  Every tile is handled exactly once whatever
+// the hardware placement; the XCD split only decides locality.
+template <class P, int T, int DIR, int MODE, int SP, int W, typename R>
+__global__ void __launch_bounds__(P::G* T, W) k_colfft_p(ColArgs a)
+{
+    constexpr int N = P::N, E = P::E;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
+    cpx<R>* twl = reinterpret_cast<cpx<R>*>(smem_raw + tile_bytes<P, T, SP, R>());
+    P::template load_tw<R>(twl, static_cast<const cpx<R>*>(a.tw));
+    const int tid = threadIdx.x, c = tid % T, g = tid / T;
+    const long long ntiles = (a.Q + T - 1) / T;
+    const long long nb = gridDim.x, x = blockIdx.x % 8, j = blockIdx.x / 8;
+    const long long nbx = nb / 8 + (x < nb % 8 ? 1 : 0);
+    const long long cc = ntiles / 8, rem = ntiles % 8;
+    const long long start = x * cc + (x < rem ? x : rem), cnt = cc + (x < rem ? 1 : 0);
+
+    auto column = [&](long long tile, bool& valid, long long& off_in, long long& off_out) {
+        const long long q = tile * T + c;
+        valid = q < a.Q;
+        const long long outer = valid ? q / a.S : 0, inner = valid ? q % a.S : 0;
+        const long long sb = outer / a.nc, pc = outer % a.nc;
+        off_in = sb * a.in_ss + pc * a.in_cs + inner;
+        off_out = sb * a.out_ss + pc * a.out_cs + inner;
+    };
+    auto load = [&](long long tile, cpx<R>(&v)[E]) {
+        bool valid;
+        long long oi, oo;
+        column(tile, valid, oi, oo);
+        const cpx<R>* __restrict__ in = static_cast<const cpx<R>*>(a.in) + oi;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int n = P::in_pos(g, i);
+            int r = n;
+            if constexpr (MODE == COL_INV_PAD) r = compact_of(n, N, a.K, a.M);
+            v[i] = (valid && r >= 0) ? in[r * a.S] : cpx<R>{0, 0};
+        }
+    };
+    cpx<R> v[E], vn[E];
+    long long i = j;
+    if (i < cnt) load(start + i, vn);
+    for (; i < cnt; i += nbx) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = vn[e];
+        if (i + nbx < cnt) load(start + i + nbx, vn);
+        if constexpr (SP) P::template run<DIR, T, 1>(v, g, reinterpret_cast<cpx<R>*>(reinterpret_cast<R*>(lds) + c), twl);
+        else P::template run<DIR, T, 0>(v, g, lds + c, twl);
+        bool valid;
+        long long oi, oo;
+        column(start + i, valid, oi, oo);
+        cpx<R>* __restrict__ out = static_cast<cpx<R>*>(a.out) + oo;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int n = P::out_pos(g, e);
+            if constexpr (MODE == COL_INV_PAD) {
+                if (valid) out[n * a.S] = v[e];
+            } else {
+                const int r = compact_of(n, N, a.K, a.M);
+                if (valid && r >= 0) out[r * a.S] = cscale(v[e], (R)a.scale);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ X pass
 // Two real lines l1 = 2u, l2 = 2u+1 share one complex transform: for a C2R,
 // Z = A + iB with A, B the Hermitian half spectra gives z = a + i b; for an
@@ -89,8 +155,10 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
     static_assert(PF::R0 == PI::RL, "forward plan must start with the inverse plan's last radix");
     constexpr int LL = PI::lds_len > PF::lds_len ? PI::lds_len : PF::lds_len;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cpx<R>* tw = reinterpret_cast<cpx<R>*>(smem_raw) + U * LL;
-    load_twiddles(tw, static_cast<const cpx<R>*>(a.tw), N);
+    cpx<R>* twI = reinterpret_cast<cpx<R>*>(smem_raw) + U * LL;
+    cpx<R>* twF = twI + PI::tw_len;
+    PI::template load_tw<R>(twI, static_cast<const cpx<R>*>(a.tw));
+    PF::template load_tw<R>(twF, static_cast<const cpx<R>*>(a.tw));
     const int tid = threadIdx.x, u = tid / G, t = tid % G;
     cpx<R>* my = reinterpret_cast<cpx<R>*>(smem_raw) + u * LL;
     const long long unit = xcd_tile(gridDim.x) * U + u;
@@ -100,8 +168,9 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
     const long long l1 = L % ((long long)N * N);
     const int K = a.K, Mx = K + 1;
 
-    // inverse (C2R) of component c of both lines into z = a + i b
-    auto load_inv = [&](int c, cpx<R>(&v)[E]) {
+    // inverse (C2R) of component c of both lines into z = a + i b: the
+    // Hermitian input of the packed transform, then the transform
+    auto load_raw = [&](int c, cpx<R>(&v)[E]) {
         const cpx<R>* p1 = static_cast<const cpx<R>*>(a.in) + samp * a.in_ss + c * a.in_cs + l1 * Mx;
         const cpx<R>* p2 = p1 + Mx;
 #pragma unroll
@@ -121,12 +190,15 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
             }
             v[i] = {A.x - B.y, A.y + B.x};
         }
-        PI::template run<+1, 1>(v, t, my, tw);
+    };
+    auto load_inv = [&](int c, cpx<R>(&v)[E]) {
+        load_raw(c, v);
+        PI::template run<+1, 1>(v, t, my, twI);
     };
 
     // forward (R2C) of v = a + i b; store k_x <= K of both lines as product p
     auto fwd_store = [&](int p, cpx<R>(&v)[E]) {
-        PF::template run<-1, 1>(v, t, my, tw);
+        PF::template run<-1, 1>(v, t, my, twF);
 #pragma unroll
         for (int i = 0; i < E; ++i) my[lds_pos<PF::R0>(PF::out_pos(t, i))] = v[i];
         __syncthreads();
@@ -146,9 +218,13 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
 
     if constexpr (MODE == X_RHS) {
         cpx<R> z0[E], z1[E], z2[E], v[E];
-        load_inv(0, z0);
-        load_inv(1, z1);
-        load_inv(2, z2);
+        // all three loads in flight before the first transform
+        load_raw(0, z0);
+        load_raw(1, z1);
+        load_raw(2, z2);
+        PI::template run<+1, 1>(z0, t, my, twI);
+        PI::template run<+1, 1>(z1, t, my, twI);
+        PI::template run<+1, 1>(z2, t, my, twI);
         // B_ij = u_i u_j, upper triangle (xx, xy, xz, yy, yz, zz); real parts
         // belong to line l1, imaginary parts to line l2
 #pragma unroll 1
@@ -236,7 +312,7 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     cpx<R>* twl = reinterpret_cast<cpx<R>*>(smem_raw + tile_bytes<P, T, SP, R>());
-    load_twiddles(twl, static_cast<const cpx<R>*>(a.tw), N);
+    P::template load_tw<R>(twl, static_cast<const cpx<R>*>(a.tw));
     const int tid = threadIdx.x, c = tid % T, g = tid / T;
     const long long q = xcd_tile(gridDim.x) * T + c;
     const bool valid = q < a.Q;
@@ -406,10 +482,34 @@ template <class P, int T, int DIR, int MODE, int SP, int W, typename R>
 hipError_t launch_col(const ColArgs& a, hipStream_t s)
 {
     static_assert(P::G * T <= 1024, "at most 1024 threads per block");
-    static_assert(tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::N <= 163840, "LDS per block exceeds 160 KiB");
+    static_assert(tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len <= 163840, "LDS per block exceeds 160 KiB");
     static bool done = false;
     return launch_k(k_colfft<P, T, DIR, MODE, SP, W, R>, (a.Q + T - 1) / T, P::G * T,
-                    tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::N, s, a, done);
+                    tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len, s, a, done);
+}
+
+inline int device_cus()
+{
+    static int n = 0;
+    if (n == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    }
+    return n;
+}
+
+// persistent column pass with BPC resident blocks per compute unit
+template <class P, int T, int DIR, int MODE, int SP, int W, int BPC, typename R>
+hipError_t launch_col_p(const ColArgs& a, hipStream_t s)
+{
+    static_assert(P::G * T <= 1024, "at most 1024 threads per block");
+    static_assert(tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len <= 163840, "LDS per block exceeds 160 KiB");
+    static bool done = false;
+    const long long ntiles = (a.Q + T - 1) / T;
+    long long grid = (long long)device_cus() * BPC;
+    if (grid > ntiles) grid = ntiles;
+    return launch_k(k_colfft_p<P, T, DIR, MODE, SP, W, R>, grid, P::G * T,
+                    tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len, s, a, done);
 }
 
 template <class PI, class PF, int U, int MODE, int W, typename R>
@@ -417,20 +517,20 @@ hipError_t launch_x(const XArgs& a, hipStream_t s)
 {
     constexpr int XL = PI::lds_len > PF::lds_len ? PI::lds_len : PF::lds_len;
     static_assert(PI::G * U <= 1024, "at most 1024 threads per block");
-    static_assert(sizeof(cpx<R>) * (XL * U + PI::N) <= 163840, "LDS per block exceeds 160 KiB");
+    static_assert(sizeof(cpx<R>) * (XL * U + PI::tw_len + PF::tw_len) <= 163840, "LDS per block exceeds 160 KiB");
     static bool done = false;
     return launch_k(k_xline<PI, PF, U, MODE, W, R>, (a.nunits + U - 1) / U, PI::G * U,
-                    sizeof(cpx<R>) * (XL * U + PI::N), s, a, done);
+                    sizeof(cpx<R>) * (XL * U + PI::tw_len + PF::tw_len), s, a, done);
 }
 
 template <class P, int T, int MODE, int SP, int W, typename R>
 hipError_t launch_f3(const F3Args& a, hipStream_t s)
 {
     static_assert(P::G * T <= 1024, "at most 1024 threads per block");
-    static_assert(tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::N <= 163840, "LDS per block exceeds 160 KiB");
+    static_assert(tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len <= 163840, "LDS per block exceeds 160 KiB");
     static bool done = false;
     return launch_k(k_f3<P, T, MODE, SP, W, R>, (a.Q + T - 1) / T, P::G * T,
-                    tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::N, s, a, done);
+                    tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len, s, a, done);
 }
 
 // Epilogue of the split F3 schedule: the six truncated, scaled components
@@ -500,12 +600,13 @@ __global__ void __launch_bounds__(256) k_f3_epilogue(F3Args a)
 
 // Split F3 schedule: forward z of the six components with truncation into
 // scratch (a column pass), then the pointwise epilogue.
-template <class P, int T, int SP, int W, typename R>
+template <class P, int T, int SP, int W, int BPC, typename R>
 hipError_t launch_f3_split(const F3Args& a, hipStream_t s)
 {
     const long long B = a.Q / a.MMx, MM = (long long)a.M * a.MMx;
     ColArgs c{a.in, a.scratch, a.tw, a.Q * 6, a.MMx, 6, a.in_cs, a.in_ss, MM, 6 * MM, a.K, a.M, a.scale};
-    hipError_t e = launch_col<P, T, -1, COL_FWD_TRUNC, SP, W, R>(c, s);
+    hipError_t e = BPC > 0 ? launch_col_p<P, T, -1, COL_FWD_TRUNC, SP, W, (BPC > 0 ? BPC : 1), R>(c, s)
+                           : launch_col<P, T, -1, COL_FWD_TRUNC, SP, W, R>(c, s);
     if (e != hipSuccess) return e;
     const long long total = B * MM;
     hipLaunchKernelGGL(k_f3_epilogue<R>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);

@@ -67,6 +67,7 @@ struct Group {
     void *A = nullptr, *Bw = nullptr, *C = nullptr;  // pass workspaces
     void *tw = nullptr, *rate = nullptr;
     double *dt = nullptr, *ones = nullptr;
+    std::vector<double> dt_host;  // values last uploaded to dt
     // adjoint buffers (allocated on first use): stage u2, adjoint stages,
     // strain, and 9-component pass workspaces
     void *U2 = nullptr, *L1 = nullptr, *L2 = nullptr, *L3 = nullptr, *Sb = nullptr, *A9 = nullptr, *B9 = nullptr;
@@ -400,9 +401,11 @@ ns_status set_dt(ns_ctx* c, const double* dt)
     for (Group& g : c->groups) {
         std::vector<double> v(g.B);
         for (int b = 0; b < g.B; ++b) v[b] = dt[g.samples[b]];
+        if (v == g.dt_host) continue;  // already on the device
         HIP_TRY(c, hipMemcpyAsync(g.dt, v.data(), sizeof(double) * g.B, hipMemcpyHostToDevice, c->stream));
         // the host vector dies here: wait for the copy
         HIP_TRY(c, hipStreamSynchronize(c->stream));
+        g.dt_host = v;
     }
     return NS_OK;
 }
@@ -461,17 +464,43 @@ ns_status run_vjp(ns_ctx* c, Group& g, const void* u, const void* lam, void* out
     return NS_OK;
 }
 
-// Adjoint of one SSP-RK3 step for a group: stage states u^n, u1, u2 in U0,
-// U1, U2; lambda_{n+1} in L3 on entry, lambda_n in L3 on return.
-ns_status adjoint_rk3(ns_ctx* c, Group& g)
+// Adjoint of one SSP-RK3 step for a group: stage states u^n, u1, u2 (compact,
+// batch-contiguous); lambda_{n+1} in L3 on entry, lambda_n in L3 on return.
+ns_status adjoint_rk3(ns_ctx* c, Group& g, const void* un, const void* u1, const void* u2)
 {
     ns_status st;
     // lambda_2 = 2/3 lambda_3 + 2/3 dt F'(u2)^T lambda_3
-    if ((st = run_vjp(c, g, g.U2, g.L3, g.L2, 2.0 / 3.0, 0.0, 0.0, 2.0 / 3.0, g.dt))) return st;
+    if ((st = run_vjp(c, g, u2, g.L3, g.L2, 2.0 / 3.0, 0.0, 0.0, 2.0 / 3.0, g.dt))) return st;
     // lambda_1 = 1/4 lambda_2 + 1/4 dt F'(u1)^T lambda_2
-    if ((st = run_vjp(c, g, g.U1, g.L2, g.L1, 0.0, 0.25, 0.0, 0.25, g.dt))) return st;
+    if ((st = run_vjp(c, g, u1, g.L2, g.L1, 0.0, 0.25, 0.0, 0.25, g.dt))) return st;
     // lambda_n = 1/3 lambda_3 + 3/4 lambda_2 + lambda_1 + dt F'(u^n)^T lambda_1
-    if ((st = run_vjp(c, g, g.U0, g.L1, g.L3, 1.0 / 3.0, 0.75, 1.0, 1.0, g.dt))) return st;
+    if ((st = run_vjp(c, g, un, g.L1, g.L3, 1.0 / 3.0, 0.75, 1.0, 1.0, g.dt))) return st;
+    return NS_OK;
+}
+
+// Stage states of tape step `step` for a group: read in place when the group
+// holds one sample (the tape layout is the compact layout), else gathered
+// into U0..U2.
+ns_status tape_stages(ns_ctx* c, Group& g, const void* const* tape, size_t step_bytes, int step, const void** un,
+                      const void** u1, const void** u2)
+{
+    const size_t one = g.st * 2 * c->rsz;
+    if (g.B == 1) {
+        const char* base = (const char*)tape[g.samples[0]] + (size_t)step * step_bytes;
+        *un = base;
+        *u1 = base + one;
+        *u2 = base + 2 * one;
+        return NS_OK;
+    }
+    void* dst[3] = {g.U0, g.U1, g.U2};
+    for (int b = 0; b < g.B; ++b)
+        for (int k = 0; k < 3; ++k)
+            HIP_TRY(c, hipMemcpyAsync((char*)dst[k] + b * one,
+                                      (const char*)tape[g.samples[b]] + (size_t)step * step_bytes + k * one, one,
+                                      hipMemcpyDeviceToDevice, c->stream));
+    *un = g.U0;
+    *u1 = g.U1;
+    *u2 = g.U2;
     return NS_OK;
 }
 
@@ -1007,12 +1036,9 @@ ns_status ns_adjoint_step(ns_ctx* c, const void* const* uh, const void* const* t
     const size_t sb = 2 * c->rsz;
     for (Group& g : c->groups) {
         const size_t one = g.st * sb;
+        const void *un = g.U0, *u1 = g.U1, *u2 = g.U2;
         if (tape_step) {
-            void* dst[3] = {g.U0, g.U1, g.U2};
-            for (int b = 0; b < g.B; ++b)
-                for (int k = 0; k < 3; ++k)
-                    HIP_TRY(c, hipMemcpyAsync((char*)dst[k] + b * one, (const char*)tape_step[g.samples[b]] + k * one,
-                                              one, hipMemcpyDeviceToDevice, c->stream));
+            if ((st = tape_stages(c, g, tape_step, 0, 0, &un, &u1, &u2))) return st;
         } else {
             for (int b = 0; b < g.B; ++b)
                 HIP_TRY(c, launch_pack(c->f64, uh[g.samples[b]], (char*)g.U0 + b * one, g.N, g.K, c->stream));
@@ -1021,7 +1047,35 @@ ns_status ns_adjoint_step(ns_ctx* c, const void* const* uh, const void* const* t
         }
         for (int b = 0; b < g.B; ++b)
             HIP_TRY(c, launch_pack(c->f64, lam[g.samples[b]], (char*)g.L3 + b * one, g.N, g.K, c->stream));
-        if ((st = adjoint_rk3(c, g))) return st;
+        if ((st = adjoint_rk3(c, g, un, u1, u2))) return st;
+        for (int b = 0; b < g.B; ++b)
+            HIP_TRY(c, launch_unpack(c->f64, (const char*)g.L3 + b * one, lam[g.samples[b]], g.N, g.K, c->stream));
+    }
+    return NS_OK;
+}
+
+ns_status ns_adjoint_steps(ns_ctx* c, const void* const* tape, int32_t nsteps, const double* dt, void* const* lam)
+{
+    CHECK_STATE(c);
+    ns_status st;
+    if ((st = check_ptrs(c, (const void* const*)lam, "lam")) || (st = check_ptrs(c, tape, "tape")) ||
+        (st = check_dt(c, dt)))
+        return st;
+    if (nsteps < 0) return fail(c, NS_ERR_ARG, "nsteps = %d must be >= 0", nsteps);
+    if (nsteps == 0) return NS_OK;
+    for (Group& g : c->groups)
+        if ((st = ensure_adjoint_buffers(c, g))) return st;
+    if ((st = set_dt(c, dt))) return st;
+    const size_t sb = 2 * c->rsz;
+    for (Group& g : c->groups) {
+        const size_t one = g.st * sb;
+        for (int b = 0; b < g.B; ++b)
+            HIP_TRY(c, launch_pack(c->f64, lam[g.samples[b]], (char*)g.L3 + b * one, g.N, g.K, c->stream));
+        for (int step = nsteps - 1; step >= 0; --step) {
+            const void *un, *u1, *u2;
+            if ((st = tape_stages(c, g, tape, tape_step_bytes(c, g), step, &un, &u1, &u2))) return st;
+            if ((st = adjoint_rk3(c, g, un, u1, u2))) return st;
+        }
         for (int b = 0; b < g.B; ++b)
             HIP_TRY(c, launch_unpack(c->f64, (const char*)g.L3 + b * one, lam[g.samples[b]], g.N, g.K, c->stream));
     }

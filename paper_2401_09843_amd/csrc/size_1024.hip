@@ -20,6 +20,10 @@ SizeKernels make32()
     add_col<PA, 16, 0, 1, R>(k, "G64 r16.16.4 T16");
     add_col<PB, 8, 0, 1, R>(k, "G128 r8.8.4.4 T8");
     add_col<PB, 8, 1, 1, R>(k, "G128 r8.8.4.4 T8 split");
+    add_col_p<PA, 8, 0, 1, 2, R>(k, "persistent G64 r16.16.4 T8 x2");
+    add_col_p<PA, 8, 1, 1, 2, R>(k, "persistent G64 r16.16.4 T8 split x2");
+    add_col_p<PB, 8, 1, 1, 2, R>(k, "persistent G128 r8.8.4.4 T8 split x2");
+    add_col_p<PA, 16, 1, 1, 1, R>(k, "persistent G64 r16.16.4 T16 split x1");
     add_x<PB, PBR, 2, 3, R>(k, "G128 r8.8.4.4 U2 w3");
     add_x<PB, PBR, 1, 1, R>(k, "G128 r8.8.4.4 U1");
     add_x<PB, PBR, 4, 1, R>(k, "G128 r8.8.4.4 U4");
@@ -34,7 +38,9 @@ SizeKernels make32()
     add_f3<PC, 8, 1, 1, R>(k, "G64 r16.16.4 T8 split");
     add_f3<PD, 4, 0, 1, R>(k, "G256 r4.4.4.4.4 T4");
     add_f3<PD, 2, 0, 1, R>(k, "G256 r4.4.4.4.4 T2");
-    add_f3_split<PA, 16, 1, 1, R>(k, "split: G64 r16.16.4 T16 split + epilogue");
+    add_f3_split<PA, 16, 1, 1, 0, R>(k, "split: G64 r16.16.4 T16 split + epilogue");
+    add_f3_split<PA, 8, 0, 1, 2, R>(k, "split: persistent G64 r16.16.4 T8 x2 + epilogue");
+    add_f3_split<PB, 8, 1, 1, 2, R>(k, "split: persistent G128 r8.8.4.4 T8 split x2 + epilogue");
     return k;
 }
 

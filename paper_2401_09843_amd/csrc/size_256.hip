@@ -17,6 +17,8 @@ SizeKernels make32()
     add_col<PA, 64, 0, 1, R>(k, "G16 r16.16 T64");
     add_col<PB, 16, 0, 1, R>(k, "G32 r8.8.4 T16");
     add_col<PB, 32, 0, 1, R>(k, "G32 r8.8.4 T32");
+    add_col_p<PA, 16, 0, 1, 4, R>(k, "persistent G16 r16.16 T16 x4");
+    add_col_p<PA, 32, 0, 1, 2, R>(k, "persistent G16 r16.16 T32 x2");
     add_x<PB, PBR, 4, 1, R>(k, "G32 r8.8.4 U4");
     add_x<PB, PBR, 8, 1, R>(k, "G32 r8.8.4 U8");
     add_x<PA, PA, 4, 1, R>(k, "G16 r16.16 U4");
@@ -25,7 +27,7 @@ SizeKernels make32()
     add_f3<PB, 16, 0, 1, R>(k, "G32 r8.8.4 T16");
     add_f3<PA, 16, 0, 1, R>(k, "G16 r16.16 T16");
     add_f3<PC, 4, 0, 1, R>(k, "G64 r4.4.4.4 T4");
-    add_f3_split<PA, 16, 0, 1, R>(k, "split: G16 r16.16 T16 + epilogue");
+    add_f3_split<PA, 16, 0, 1, 0, R>(k, "split: G16 r16.16 T16 + epilogue");
     return k;
 }
 

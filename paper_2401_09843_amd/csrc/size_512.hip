@@ -18,6 +18,8 @@ SizeKernels make32()
     add_col<PA, 16, 1, 1, R>(k, "G64 r8.8.8 T16 split");
     add_col<PB, 16, 0, 1, R>(k, "G32 r16.8.4 T16");
     add_col<PB, 32, 1, 1, R>(k, "G32 r16.8.4 T32 split");
+    add_col_p<PA, 8, 0, 1, 2, R>(k, "persistent G64 r8.8.8 T8 x2");
+    add_col_p<PA, 16, 0, 1, 1, R>(k, "persistent G64 r8.8.8 T16 x1");
     add_x<PA, PA, 2, 1, R>(k, "G64 r8.8.8 U2");
     add_x<PA, PA, 4, 3, R>(k, "G64 r8.8.8 U4 w3");
     add_x<PB, PBR, 4, 1, R>(k, "G32 r16.8.4 U4");
@@ -26,7 +28,7 @@ SizeKernels make32()
     add_f3<PA, 8, 1, 1, R>(k, "G64 r8.8.8 T8 split");
     add_f3<PC, 4, 0, 1, R>(k, "G128 r4.4.4.4.2 T4");
     add_f3<PB, 8, 0, 1, R>(k, "G32 r16.8.4 T8");
-    add_f3_split<PA, 16, 0, 1, R>(k, "split: G64 r8.8.8 T16 + epilogue");
+    add_f3_split<PA, 16, 0, 1, 0, R>(k, "split: G64 r8.8.8 T16 + epilogue");
     return k;
 }
 

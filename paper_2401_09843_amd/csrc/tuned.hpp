@@ -11,6 +11,13 @@ void add_col(SizeKernels& k, const char* name)
     add_variant(k.fwd, k.n_fwd, launch_col<P, T, -1, COL_FWD_TRUNC, SP, W, R>, name);
 }
 
+template <class P, int T, int SP, int W, int BPC, typename R>
+void add_col_p(SizeKernels& k, const char* name)
+{
+    add_variant(k.inv, k.n_inv, launch_col_p<P, T, +1, COL_INV_PAD, SP, W, BPC, R>, name);
+    add_variant(k.fwd, k.n_fwd, launch_col_p<P, T, -1, COL_FWD_TRUNC, SP, W, BPC, R>, name);
+}
+
 template <class PI, class PF, int U, int W, typename R>
 void add_x(SizeKernels& k, const char* name)
 {
@@ -23,10 +30,10 @@ void add_f3(SizeKernels& k, const char* name)
     add_variant(k.f3, k.n_f3, launch_f3<P, T, F3_RHS, SP, W, R>, name);
 }
 
-template <class P, int T, int SP, int W, typename R>
+template <class P, int T, int SP, int W, int BPC, typename R>
 void add_f3_split(SizeKernels& k, const char* name)
 {
-    add_variant(k.f3, k.n_f3, launch_f3_split<P, T, SP, W, R>, name);
+    add_variant(k.f3, k.n_f3, launch_f3_split<P, T, SP, W, BPC, R>, name);
 }
 
 }  // namespace ns

@@ -22,7 +22,7 @@ NS_USE_GRAPH, NS_CHECK_FINITE, NS_NO_TUNE = 1, 2, 4
 
 # every symbol the header declares
 EXPORTS = ("ns_init", "ns_destroy", "ns_last_error", "ns_workspace_bytes", "ns_supported_sizes", "ns_forward",
-           "ns_inverse", "ns_project", "ns_rhs", "ns_step", "ns_tape_bytes", "ns_step_taped", "ns_adjoint_step",
+           "ns_inverse", "ns_project", "ns_rhs", "ns_step", "ns_tape_bytes", "ns_step_taped", "ns_adjoint_step", "ns_adjoint_steps",
            "ns_energy_spectrum", "ns_sync", "ns_profile", "ns_profile_read", "ns_variant_count", "ns_set_variant",
            "ns_tune_report")
 NS_NPASS = 5
@@ -68,6 +68,7 @@ def lib() -> ctypes.CDLL:
             "ns_tape_bytes": [P, I32, ctypes.POINTER(S)],
             "ns_step_taped": [P, PP, PD, I32, PP],
             "ns_adjoint_step": [P, PP, PP, PD, PP],
+            "ns_adjoint_steps": [P, PP, I32, PD, PP],
             "ns_energy_spectrum": [P, PP, P, I32],
             "ns_sync": [P],
             "ns_profile": [P, I32],
@@ -236,6 +237,18 @@ class Solver:
             self._check(self._L.ns_adjoint_step(self._ctx, _ptrs(us), None, arr, _ptrs(ls)))
         return lam
 
+    def adjoint_steps(self, lam, dt, tape, nsteps: int):
+        """nsteps adjoint steps backward through a tape from step_taped."""
+        ls = self._spec(self._list(lam))
+        dts = [float(dt)] * len(ls) if not isinstance(dt, (list, tuple)) else [float(v) for v in dt]
+        arr = (ctypes.c_double * len(dts))(*dts)
+        tps = self._list(tape)
+        for t, n in zip(tps, self.sizes):
+            if t.device != self.device or t.numel() < nsteps * self.tape_step_bytes(n):
+                raise ValueError("tape too small")
+        self._check(self._L.ns_adjoint_steps(self._ctx, _ptrs(tps), int(nsteps), arr, _ptrs(ls)))
+        return lam
+
     def spectrum(self, uhat, kbins: int):
         xs = self._spec(self._list(uhat))
         E = torch.zeros((len(xs), kbins), dtype=torch.float64, device=self.device)
@@ -290,10 +303,13 @@ class Solver:
 
 class _Rollout(torch.autograd.Function):
     """u0 (physical) -> u(T) (physical) after nsteps SSP-RK3 steps, with the
-    discrete adjoint in backward.  The forward keeps the state every
-    `ckpt_every` steps; the backward re-runs each segment from its
-    checkpoint with the stage states taped, then steps the adjoint back
-    through the tape.  The last segment is taped during the forward pass.
+    discrete adjoint in backward.  The trajectory is cut into segments of
+    `ckpt_every` steps.  If the stage tape of the whole trajectory fits the
+    memory budget it is recorded during the forward pass and the backward
+    only runs the adjoint; otherwise the forward keeps the state at each
+    segment start and the backward re-runs each segment taped (the last
+    segment is taped during the forward pass) before stepping the adjoint
+    back through it.
 
     Gradient algebra: u(T) = F^-1[T u-hat(T)] and u-hat(0) = T P F[u0], with
     F normalised by N^-3.  In the inner product Re sum_k conj(a_k) b_k the
@@ -305,44 +321,50 @@ class _Rollout(torch.autograd.Function):
     on its own)."""
 
     @staticmethod
-    def forward(ctx, u0, solver, dt, nsteps, ckpt_every):
+    def forward(ctx, u0, solver, dt, nsteps, ckpt_every, tape_budget):
         uh = solver.forward(u0.detach().contiguous())
-        ckpts = []
         starts = list(range(0, nsteps, ckpt_every))
-        last_tape = None
+        total = nsteps * solver.tape_step_bytes(solver.sizes[0])
+        tape_all = total <= tape_budget
+        segs = []
         for i, s0 in enumerate(starts):
             length = min(ckpt_every, nsteps - s0)
-            ckpts.append((uh.clone(), length))
-            if i == len(starts) - 1:
-                last_tape = solver.new_tape(length)[0]
-                solver.step_taped(uh, dt, length, last_tape)
+            if tape_all or i == len(starts) - 1:
+                tape = solver.new_tape(length)[0]
+                segs.append((None, length, tape))
+                solver.step_taped(uh, dt, length, tape)
             else:
+                segs.append((uh.clone(), length, None))
                 solver.step(uh, dt, length)
-        ctx.solver, ctx.dt, ctx.ckpts, ctx.last_tape = solver, dt, ckpts, last_tape
+        ctx.solver, ctx.dt, ctx.segs = solver, dt, segs
         return solver.inverse(uh)
 
     @staticmethod
     def backward(ctx, g):
         S, dt = ctx.solver, ctx.dt
         lam = S.forward(g.detach().contiguous().to(S.dtype))
-        for i in reversed(range(len(ctx.ckpts))):
-            uh0, length = ctx.ckpts[i]
-            if i == len(ctx.ckpts) - 1 and ctx.last_tape is not None:
-                tape = ctx.last_tape
-            else:
+        for i in reversed(range(len(ctx.segs))):
+            uh0, length, tape = ctx.segs[i]
+            if tape is None:
                 tape = S.new_tape(length)[0]
-                S.step_taped(uh0.clone(), dt, length, tape)
-            for j in reversed(range(length)):
-                S.adjoint_step(lam, dt, tape=tape, step=j)
+                S.step_taped(uh0, dt, length, tape)
+            S.adjoint_steps(lam, dt, tape, length)
+            ctx.segs[i] = None
             del tape
-        ctx.last_tape = None
         S.project(lam)
-        return S.inverse(lam), None, None, None, None
+        return S.inverse(lam), None, None, None, None, None
 
 
-def rollout(u0: torch.Tensor, solver: "Solver", dt: float, nsteps: int, ckpt_every: int = 20) -> torch.Tensor:
+def rollout(u0: torch.Tensor, solver: "Solver", dt: float, nsteps: int, ckpt_every: int = 20,
+            tape_budget: int = None) -> torch.Tensor:
     """Differentiable SSP-RK3 trajectory of a single-sample solver:
-    physical u0 [3,N,N,N] -> physical u(T) after nsteps steps of size dt."""
+    physical u0 [3,N,N,N] -> physical u(T) after nsteps steps of size dt.
+    tape_budget: bytes of device memory the full stage tape may use to avoid
+    recomputation (default: a quarter of the free device memory; 0 forces
+    checkpointing with recomputation every ckpt_every steps)."""
     if len(solver.sizes) != 1:
         raise ValueError("rollout needs a single-sample solver")
-    return _Rollout.apply(u0, solver, float(dt), int(nsteps), int(ckpt_every))
+    if tape_budget is None:
+        free, _ = torch.cuda.mem_get_info(solver.device)
+        tape_budget = free // 4
+    return _Rollout.apply(u0, solver, float(dt), int(nsteps), int(ckpt_every), int(tape_budget))
