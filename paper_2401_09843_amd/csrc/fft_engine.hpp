@@ -224,10 +224,36 @@ struct Radices<> {
 template <int PD>
 __device__ __forceinline__ int lds_pos(int pos) { return pos + pos / PD; }
 
+// LDS slot of element pos in the exchange that follows a stage of span P
+// and radix R, for ES-byte LDS elements.  PD > 0: the padded layout above.
+// PD == 0: a per-stage padding.  The LDS serves 256 bytes (64 banks of 4
+// bytes) per cycle, i.e. a row of W = 256 / ES elements.  The stage writes
+// element (b - k) R + k + m P from lane b (k = b mod P); adding P slots
+// after every D = max(W, P R) elements spreads the lanes that share k over
+// the P-slot groups of a row, while the unit-stride reads of the next stage
+// stay inside one row.  The padding is a multiple of P and constant over
+// each block of D elements, so m P and the tile offsets stay immediate
+// address offsets.  Stages with P >= W write at unit stride and need none.
+template <int PD, int P, int R, int ES>
+__device__ __forceinline__ int lds_slot(int pos)
+{
+    if constexpr (PD > 0) {
+        return pos + pos / PD;
+    } else {
+        constexpr int W = 256 / ES;
+        if constexpr (P >= W) {
+            return pos;
+        } else {
+            constexpr int D = P * R > W ? P * R : W;
+            return pos + P * (pos / D);
+        }
+    }
+}
+
 // Stage s of a transform of length N held by G threads: compute the
 // butterflies, then (unless it is the last stage) exchange through LDS into
 // the register layout of the next stage.  lds points at this line's slot 0;
-// element pos lives at lds[lds_pos<PD>(pos) * LS].  With SP = 1 the
+// element pos lives at lds[lds_slot<PD, P, R, ES>(pos) * LS].  With SP = 1 the
 // exchange moves the real and then the imaginary parts through a real-valued
 // buffer of the same layout (half the LDS, twice the barriers).
 template <int N, int G, int DIR, int PD, int LS, int SP, typename T, int P, int OFF, int... Rs>
@@ -248,13 +274,13 @@ struct Stages<N, G, DIR, PD, LS, SP, T, P, OFF, R, Rest...> {
             const int k = b % P;
             const int j = (b - k) * R + k;
 #pragma unroll
-            for (int m = 0; m < R; ++m) lds[lds_pos<PD>(j + m * P) * LS] = get(v[q * R + m]);
+            for (int m = 0; m < R; ++m) lds[lds_slot<PD, P, R, sizeof(L)>(j + m * P) * LS] = get(v[q * R + m]);
         }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < N / (R2 * G); ++q)
 #pragma unroll
-            for (int m = 0; m < R2; ++m) put(v[q * R2 + m], lds[lds_pos<PD>(t + q * G + m * (N / R2)) * LS]);
+            for (int m = 0; m < R2; ++m) put(v[q * R2 + m], lds[lds_slot<PD, P, R, sizeof(L)>(t + q * G + m * (N / R2)) * LS]);
         __syncthreads();
     }
 
@@ -334,10 +360,32 @@ struct Plan<N_, G_, Radices<Rs...>> {
         __syncthreads();
     }
 
-    template <int DIR, int LS, int SP = 0, typename T>
+    // LDS elements per line with the per-stage padding (lds_slot, PD = 0)
+    // for ES-byte elements
+    template <int ES>
+    static constexpr int lds_len_st()
+    {
+        constexpr int rad[] = {Rs...};
+        constexpr int W = 256 / ES;
+        int P = 1, ext = N_;
+        for (int s = 0; s + 1 < (int)sizeof...(Rs); ++s) {
+            const int R = rad[s];
+            if (P < W) {
+                const int D = P * R > W ? P * R : W;
+                const int e = N_ + P * ((N_ - 1) / D);
+                ext = e > ext ? e : ext;
+            }
+            P *= R;
+        }
+        return ext;
+    }
+
+    // ST = true selects the per-stage padding (for LS = 1)
+    template <int DIR, int LS, int SP = 0, bool ST = false, typename T>
     __device__ __forceinline__ static void run(cpx<T> (&v)[E], int t, cpx<T>* lds, const cpx<T>* __restrict__ tw)
     {
-        Stages<N_, G_, DIR, R0, LS, SP, T, 1, 0, Rs...>::run(v, t, lds, tw);
+        static_assert(!ST || (LS == 1 && SP == 0), "per-stage padding is laid out for one line at unit stride");
+        Stages<N_, G_, DIR, ST ? 0 : R0, LS, SP, T, 1, 0, Rs...>::run(v, t, lds, tw);
     }
     // position of register element i = q * R + m at stage-0 input / final output
     __device__ __forceinline__ static constexpr int in_pos(int t, int i) { return t + (i / R0) * G + (i % R0) * (N / R0); }

@@ -29,6 +29,14 @@ __device__ __forceinline__ int compact_of(int n, int N, int K, int M)
     return n <= K ? n : (n >= N - K ? n - N + M : -1);
 }
 
+// The 2/3-rule cutoff K = floor((N - 1) / 3) and compact length M = 2K + 1
+// are fixed by N; the kernels take them as constants (the launchers reject
+// arguments that disagree).
+template <int N>
+struct Cut {
+    static constexpr int K = (N - 1) / 3, M = 2 * K + 1;
+};
+
 // ------------------------------------------------------------------ I1/I2/F2
 // LDS bytes of a column tile (complex or split exchange), 16-byte aligned
 template <class P, int T, int SP, typename R>
@@ -40,7 +48,7 @@ constexpr size_t tile_bytes()
 template <class P, int T, int DIR, int MODE, int SP, int W, typename R>
 __global__ void __launch_bounds__(P::G* T, W) k_colfft(ColArgs a)
 {
-    constexpr int N = P::N, E = P::E;
+    constexpr int N = P::N, E = P::E, KC = Cut<N>::K, MC = Cut<N>::M;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     cpx<R>* twl = reinterpret_cast<cpx<R>*>(smem_raw + tile_bytes<P, T, SP, R>());
@@ -59,7 +67,7 @@ __global__ void __launch_bounds__(P::G* T, W) k_colfft(ColArgs a)
     for (int i = 0; i < E; ++i) {
         const int n = P::in_pos(g, i);
         int r = n;
-        if constexpr (MODE == COL_INV_PAD) r = compact_of(n, N, a.K, a.M);
+        if constexpr (MODE == COL_INV_PAD) r = compact_of(n, N, KC, MC);
         v[i] = (valid && r >= 0) ? in[r * a.S] : cpx<R>{0, 0};
     }
     if constexpr (SP) P::template run<DIR, T, 1>(v, g, reinterpret_cast<cpx<R>*>(reinterpret_cast<R*>(lds) + c), twl);
@@ -70,7 +78,7 @@ __global__ void __launch_bounds__(P::G* T, W) k_colfft(ColArgs a)
         if constexpr (MODE == COL_INV_PAD) {
             if (valid) out[n * a.S] = v[i];
         } else {
-            const int r = compact_of(n, N, a.K, a.M);
+            const int r = compact_of(n, N, KC, MC);
             if (valid && r >= 0) out[r * a.S] = cscale(v[i], (R)a.scale);
         }
     }
@@ -83,7 +91,7 @@ __global__ void __launch_bounds__(P::G* T, W) k_colfft(ColArgs a)
 template <class P, int T, int DIR, int MODE, int SP, int W, typename R>
 __global__ void __launch_bounds__(P::G* T, W) k_colfft_p(ColArgs a)
 {
-    constexpr int N = P::N, E = P::E;
+    constexpr int N = P::N, E = P::E, KC = Cut<N>::K, MC = Cut<N>::M;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     cpx<R>* twl = reinterpret_cast<cpx<R>*>(smem_raw + tile_bytes<P, T, SP, R>());
@@ -112,7 +120,7 @@ __global__ void __launch_bounds__(P::G* T, W) k_colfft_p(ColArgs a)
         for (int i = 0; i < E; ++i) {
             const int n = P::in_pos(g, i);
             int r = n;
-            if constexpr (MODE == COL_INV_PAD) r = compact_of(n, N, a.K, a.M);
+            if constexpr (MODE == COL_INV_PAD) r = compact_of(n, N, KC, MC);
             v[i] = (valid && r >= 0) ? in[r * a.S] : cpx<R>{0, 0};
         }
     };
@@ -135,7 +143,7 @@ __global__ void __launch_bounds__(P::G* T, W) k_colfft_p(ColArgs a)
             if constexpr (MODE == COL_INV_PAD) {
                 if (valid) out[n * a.S] = v[e];
             } else {
-                const int r = compact_of(n, N, a.K, a.M);
+                const int r = compact_of(n, N, KC, MC);
                 if (valid && r >= 0) out[r * a.S] = cscale(v[e], (R)a.scale);
             }
         }
@@ -143,6 +151,14 @@ __global__ void __launch_bounds__(P::G* T, W) k_colfft_p(ColArgs a)
 }
 
 // ------------------------------------------------------------------ X pass
+// LDS elements per line of the X pass (per-stage padded exchanges)
+template <class PI, class PF, typename R>
+constexpr int x_line_len()
+{
+    constexpr int a = PI::template lds_len_st<sizeof(cpx<R>)>(), b = PF::template lds_len_st<sizeof(cpx<R>)>();
+    return a > b ? a : b;
+}
+
 // Two real lines l1 = 2u, l2 = 2u+1 share one complex transform: for a C2R,
 // Z = A + iB with A, B the Hermitian half spectra gives z = a + i b; for an
 // R2C, Z = FFT(a + i b) splits as A_k = (Z_k + conj Z_{N-k})/2,
@@ -153,7 +169,7 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
     constexpr int N = PI::N, G = PI::G, E = PI::E;
     static_assert(PF::G == G && PF::N == N, "plans must match");
     static_assert(PF::R0 == PI::RL, "forward plan must start with the inverse plan's last radix");
-    constexpr int LL = PI::lds_len > PF::lds_len ? PI::lds_len : PF::lds_len;
+    constexpr int LL = x_line_len<PI, PF, R>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<R>* twI = reinterpret_cast<cpx<R>*>(smem_raw) + U * LL;
     cpx<R>* twF = twI + PI::tw_len;
@@ -166,7 +182,7 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
     const long long L = valid ? 2 * unit : 0;
     const long long samp = L / ((long long)N * N);
     const long long l1 = L % ((long long)N * N);
-    const int K = a.K, Mx = K + 1;
+    constexpr int K = (N - 1) / 3, Mx = K + 1;
 
     // inverse (C2R) of component c of both lines into z = a + i b: the
     // Hermitian input of the packed transform, then the transform
@@ -193,21 +209,21 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
     };
     auto load_inv = [&](int c, cpx<R>(&v)[E]) {
         load_raw(c, v);
-        PI::template run<+1, 1>(v, t, my, twI);
+        PI::template run<+1, 1, 0, true>(v, t, my, twI);
     };
 
     // forward (R2C) of v = a + i b; store k_x <= K of both lines as product p
     auto fwd_store = [&](int p, cpx<R>(&v)[E]) {
-        PF::template run<-1, 1>(v, t, my, twF);
+        PF::template run<-1, 1, 0, true>(v, t, my, twF);
 #pragma unroll
-        for (int i = 0; i < E; ++i) my[lds_pos<PF::R0>(PF::out_pos(t, i))] = v[i];
+        for (int i = 0; i < E; ++i) my[PF::out_pos(t, i)] = v[i];
         __syncthreads();
         const R h = (R)(0.5 * a.scale);
         cpx<R>* o1 = static_cast<cpx<R>*>(a.out) + samp * a.out_ss + p * a.out_cs + l1 * Mx;
         cpx<R>* o2 = o1 + Mx;
         for (int kx = t; kx <= K; kx += G) {
-            const cpx<R> zk = my[lds_pos<PF::R0>(kx)];
-            const cpx<R> zm = my[lds_pos<PF::R0>((N - kx) % N)];
+            const cpx<R> zk = my[kx];
+            const cpx<R> zm = my[(N - kx) % N];
             if (valid) {
                 o1[kx] = {(zk.x + zm.x) * h, (zk.y - zm.y) * h};
                 o2[kx] = {(zk.y + zm.y) * h, (zm.x - zk.x) * h};
@@ -222,9 +238,9 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
         load_raw(0, z0);
         load_raw(1, z1);
         load_raw(2, z2);
-        PI::template run<+1, 1>(z0, t, my, twI);
-        PI::template run<+1, 1>(z1, t, my, twI);
-        PI::template run<+1, 1>(z2, t, my, twI);
+        PI::template run<+1, 1, 0, true>(z0, t, my, twI);
+        PI::template run<+1, 1, 0, true>(z1, t, my, twI);
+        PI::template run<+1, 1, 0, true>(z2, t, my, twI);
         // B_ij = u_i u_j, upper triangle (xx, xy, xz, yy, yz, zz); real parts
         // belong to line l1, imaginary parts to line l2
 #pragma unroll 1
@@ -318,7 +334,7 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
     const bool valid = q < a.Q;
     const long long samp = valid ? q / a.MMx : 0;
     const int s = valid ? (int)(q % a.MMx) : 0;
-    const int K = a.K, M = a.M, Mx = a.Mx;
+    constexpr int K = Cut<N>::K, M = Cut<N>::M, Mx = K + 1;
     const int jy = s / Mx, kxi = s % Mx;
     const int kyi = jy <= K ? jy : jy - M;
     const R kx = (R)kxi, ky = (R)kyi;
@@ -476,6 +492,13 @@ inline hipError_t launch_k(void (*k)(Args), long long blocks, int threads, size_
     return hipGetLastError();
 }
 
+// the cutoff arguments must be the ones the kernels assume for length N
+template <int N>
+inline bool cut_ok(int K, int M)
+{
+    return K == Cut<N>::K && M == Cut<N>::M;
+}
+
 // Launchers of one schedule each.  W is the minimum number of waves per
 // SIMD the compiler must allow (it caps the registers per thread).
 template <class P, int T, int DIR, int MODE, int SP, int W, typename R>
@@ -484,6 +507,7 @@ hipError_t launch_col(const ColArgs& a, hipStream_t s)
     static_assert(P::G * T <= 1024, "at most 1024 threads per block");
     static_assert(tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len <= 163840, "LDS per block exceeds 160 KiB");
     static bool done = false;
+    if (!cut_ok<P::N>(a.K, a.M)) return hipErrorInvalidValue;
     return launch_k(k_colfft<P, T, DIR, MODE, SP, W, R>, (a.Q + T - 1) / T, P::G * T,
                     tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len, s, a, done);
 }
@@ -505,6 +529,7 @@ hipError_t launch_col_p(const ColArgs& a, hipStream_t s)
     static_assert(P::G * T <= 1024, "at most 1024 threads per block");
     static_assert(tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len <= 163840, "LDS per block exceeds 160 KiB");
     static bool done = false;
+    if (!cut_ok<P::N>(a.K, a.M)) return hipErrorInvalidValue;
     const long long ntiles = (a.Q + T - 1) / T;
     long long grid = (long long)device_cus() * BPC;
     if (grid > ntiles) grid = ntiles;
@@ -515,10 +540,11 @@ hipError_t launch_col_p(const ColArgs& a, hipStream_t s)
 template <class PI, class PF, int U, int MODE, int W, typename R>
 hipError_t launch_x(const XArgs& a, hipStream_t s)
 {
-    constexpr int XL = PI::lds_len > PF::lds_len ? PI::lds_len : PF::lds_len;
+    constexpr int XL = x_line_len<PI, PF, R>();
     static_assert(PI::G * U <= 1024, "at most 1024 threads per block");
     static_assert(sizeof(cpx<R>) * (XL * U + PI::tw_len + PF::tw_len) <= 163840, "LDS per block exceeds 160 KiB");
     static bool done = false;
+    if (a.K != Cut<PI::N>::K) return hipErrorInvalidValue;
     return launch_k(k_xline<PI, PF, U, MODE, W, R>, (a.nunits + U - 1) / U, PI::G * U,
                     sizeof(cpx<R>) * (XL * U + PI::tw_len + PF::tw_len), s, a, done);
 }
@@ -529,6 +555,7 @@ hipError_t launch_f3(const F3Args& a, hipStream_t s)
     static_assert(P::G * T <= 1024, "at most 1024 threads per block");
     static_assert(tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len <= 163840, "LDS per block exceeds 160 KiB");
     static bool done = false;
+    if (!cut_ok<P::N>(a.K, a.M) || a.Mx != Cut<P::N>::K + 1) return hipErrorInvalidValue;
     return launch_k(k_f3<P, T, MODE, SP, W, R>, (a.Q + T - 1) / T, P::G * T,
                     tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len, s, a, done);
 }
