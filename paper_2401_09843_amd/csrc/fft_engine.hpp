@@ -319,6 +319,7 @@ struct TwTable {
     static constexpr int len = 0;
     template <typename T>
     __device__ __forceinline__ static void fill(int, cpx<T>*, const cpx<T>* __restrict__) {}
+    __device__ __forceinline__ static int src_index(int) { return 0; }
 };
 
 template <int N, int P, int R, int... Rest>
@@ -334,6 +335,12 @@ struct TwTable<N, P, R, Rest...> {
         } else {
             TwTable<N, P * R, Rest...>::fill(idx - here, dst + here, src);
         }
+    }
+    // index into the N-entry table of stage-table entry idx
+    __device__ __forceinline__ static int src_index(int idx)
+    {
+        if (idx < here) return (idx / P + 1) * (idx % P) * (N / (P * R));
+        return TwTable<N, P * R, Rest...>::src_index(idx - here);
     }
 };
 
@@ -352,12 +359,40 @@ struct Plan<N_, G_, Radices<Rs...>> {
     static constexpr int tw_len = TwTable<N_, 1, Rs...>::len;
 
     // build the stage tables in LDS from the N-entry table exp(-2 pi i e/N)
-    // (all threads of the block take part)
+    // (all threads of the block take part; load_tw also waits for the block)
+    template <typename T>
+    __device__ __forceinline__ static void fill_tw(cpx<T>* dst, const cpx<T>* __restrict__ src)
+    {
+        for (int i = threadIdx.x; i < tw_len; i += blockDim.x) TwTable<N_, 1, Rs...>::fill(i, dst, src);
+    }
     template <typename T>
     __device__ __forceinline__ static void load_tw(cpx<T>* dst, const cpx<T>* __restrict__ src)
     {
-        for (int i = threadIdx.x; i < tw_len; i += blockDim.x) TwTable<N_, 1, Rs...>::fill(i, dst, src);
+        fill_tw(dst, src);
         __syncthreads();
+    }
+    // the same in two halves for blocks of NT threads: fetch_tw issues the
+    // global reads into registers, put_tw writes them to LDS (no barrier)
+    template <int NT>
+    static constexpr int tw_per_thread = (tw_len + NT - 1) / NT;
+    template <int NT, typename T>
+    __device__ __forceinline__ static void fetch_tw(cpx<T> (&r)[tw_per_thread<NT> > 0 ? tw_per_thread<NT> : 1],
+                                                    const cpx<T>* __restrict__ src)
+    {
+#pragma unroll
+        for (int j = 0; j < tw_per_thread<NT>; ++j) {
+            const int i = threadIdx.x + j * NT;
+            if (i < tw_len) r[j] = src[TwTable<N_, 1, Rs...>::src_index(i)];
+        }
+    }
+    template <int NT, typename T>
+    __device__ __forceinline__ static void put_tw(cpx<T>* dst, const cpx<T> (&r)[tw_per_thread<NT> > 0 ? tw_per_thread<NT> : 1])
+    {
+#pragma unroll
+        for (int j = 0; j < tw_per_thread<NT>; ++j) {
+            const int i = threadIdx.x + j * NT;
+            if (i < tw_len) dst[i] = r[j];
+        }
     }
 
     // LDS elements per line with the per-stage padding (lds_slot, PD = 0)

@@ -14,6 +14,8 @@
 // thread loads whole rows of T columns (coalesced) straight into registers,
 // and only the Stockham exchanges go through LDS.
 #pragma once
+#include <type_traits>
+
 #include "args.hpp"
 #include "fft_engine.hpp"
 
@@ -52,7 +54,6 @@ __global__ void __launch_bounds__(P::G* T, W) k_colfft(ColArgs a)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     cpx<R>* twl = reinterpret_cast<cpx<R>*>(smem_raw + tile_bytes<P, T, SP, R>());
-    P::template load_tw<R>(twl, static_cast<const cpx<R>*>(a.tw));
     const int tid = threadIdx.x, c = tid % T, g = tid / T;
     const long long q = xcd_tile(gridDim.x) * T + c;
     const bool valid = q < a.Q;
@@ -62,6 +63,8 @@ __global__ void __launch_bounds__(P::G* T, W) k_colfft(ColArgs a)
     const cpx<R>* __restrict__ in = static_cast<const cpx<R>*>(a.in) + sb * a.in_ss + pc * a.in_cs + inner;
     cpx<R>* __restrict__ out = static_cast<cpx<R>*>(a.out) + sb * a.out_ss + pc * a.out_cs + inner;
 
+    // the column loads are issued before the twiddle tables are built, so
+    // that both latencies overlap
     cpx<R> v[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
@@ -70,6 +73,7 @@ __global__ void __launch_bounds__(P::G* T, W) k_colfft(ColArgs a)
         if constexpr (MODE == COL_INV_PAD) r = compact_of(n, N, KC, MC);
         v[i] = (valid && r >= 0) ? in[r * a.S] : cpx<R>{0, 0};
     }
+    P::template load_tw<R>(twl, static_cast<const cpx<R>*>(a.tw));
     if constexpr (SP) P::template run<DIR, T, 1>(v, g, reinterpret_cast<cpx<R>*>(reinterpret_cast<R*>(lds) + c), twl);
     else P::template run<DIR, T, 0>(v, g, lds + c, twl);
 #pragma unroll
@@ -163,7 +167,9 @@ constexpr int x_line_len()
 // Z = A + iB with A, B the Hermitian half spectra gives z = a + i b; for an
 // R2C, Z = FFT(a + i b) splits as A_k = (Z_k + conj Z_{N-k})/2,
 // B_k = (Z_k - conj Z_{N-k})/(2i).
-template <class PI, class PF, int U, int MODE, int W, typename R>
+// BPC > 0 (product pass only): persistent blocks, BPC per compute unit,
+// that build the twiddle tables once and then walk the tiles of U units.
+template <class PI, class PF, int U, int MODE, int W, typename R, int BPC = 0>
 __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
 {
     constexpr int N = PI::N, G = PI::G, E = PI::E;
@@ -172,16 +178,39 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
     constexpr int LL = x_line_len<PI, PF, R>();
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<R>* twI = reinterpret_cast<cpx<R>*>(smem_raw) + U * LL;
-    cpx<R>* twF = twI + PI::tw_len;
-    PI::template load_tw<R>(twI, static_cast<const cpx<R>*>(a.tw));
-    PF::template load_tw<R>(twF, static_cast<const cpx<R>*>(a.tw));
+    // one table serves both halves when they use the same plan
+    constexpr bool SAME = std::is_same<PI, PF>::value;
+    cpx<R>* twF = SAME ? twI : twI + PI::tw_len;
+    auto tables = [&] {
+        PI::template fill_tw<R>(twI, static_cast<const cpx<R>*>(a.tw));
+        if constexpr (!SAME) PF::template fill_tw<R>(twF, static_cast<const cpx<R>*>(a.tw));
+        __syncthreads();
+    };
+    // the product pass reads the table entries into registers ahead of its
+    // data loads and writes them to LDS after issuing those (a fill issued
+    // behind the data loads would wait for all of them)
+    constexpr int NT = G * U;
+    cpx<R> ti[PI::template tw_per_thread<NT> > 0 ? PI::template tw_per_thread<NT> : 1];
+    cpx<R> tf[PF::template tw_per_thread<NT> > 0 ? PF::template tw_per_thread<NT> : 1];
+    if constexpr (MODE == X_RHS && BPC == 0) {
+        PI::template fetch_tw<NT>(ti, static_cast<const cpx<R>*>(a.tw));
+        if constexpr (!SAME) PF::template fetch_tw<NT>(tf, static_cast<const cpx<R>*>(a.tw));
+    } else {
+        tables();
+    }
+    static_assert(BPC == 0 || MODE == X_RHS, "persistent blocks are for the product pass");
     const int tid = threadIdx.x, u = tid / G, t = tid % G;
     cpx<R>* my = reinterpret_cast<cpx<R>*>(smem_raw) + u * LL;
-    const long long unit = xcd_tile(gridDim.x) * U + u;
-    const bool valid = unit < a.nunits;
-    const long long L = valid ? 2 * unit : 0;
-    const long long samp = L / ((long long)N * N);
-    const long long l1 = L % ((long long)N * N);
+    long long samp = 0, l1 = 0;
+    bool valid = false;
+    auto set_tile = [&](long long tile) {
+        const long long unit = tile * U + u;
+        valid = unit < a.nunits;
+        const long long L = valid ? 2 * unit : 0;
+        samp = L / ((long long)N * N);
+        l1 = L % ((long long)N * N);
+    };
+    if constexpr (BPC == 0) set_tile(xcd_tile(gridDim.x));
     constexpr int K = (N - 1) / 3, Mx = K + 1;
 
     // inverse (C2R) of component c of both lines into z = a + i b: the
@@ -233,17 +262,23 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
     };
 
     if constexpr (MODE == X_RHS) {
+      auto body = [&] {
         cpx<R> z0[E], z1[E], z2[E], v[E];
         // all three loads in flight before the first transform
         load_raw(0, z0);
         load_raw(1, z1);
         load_raw(2, z2);
+        if constexpr (BPC == 0) {
+            PI::template put_tw<NT>(twI, ti);
+            if constexpr (!SAME) PF::template put_tw<NT>(twF, tf);
+            __syncthreads();
+        }
         PI::template run<+1, 1, 0, true>(z0, t, my, twI);
         PI::template run<+1, 1, 0, true>(z1, t, my, twI);
         PI::template run<+1, 1, 0, true>(z2, t, my, twI);
         // B_ij = u_i u_j, upper triangle (xx, xy, xz, yy, yz, zz); real parts
         // belong to line l1, imaginary parts to line l2
-#pragma unroll 1
+#pragma unroll
         for (int p = 0; p < 6; ++p) {
             auto mul = [&](const cpx<R>(&za)[E], const cpx<R>(&zb)[E]) {
 #pragma unroll
@@ -259,6 +294,17 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
             }
             fwd_store(p, v);
         }
+      };
+      if constexpr (BPC > 0) {
+          const long long ntiles = (a.nunits + U - 1) / U;
+#pragma unroll 1
+          for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+              set_tile(tile);
+              body();
+          }
+      } else {
+          body();
+      }
     } else if constexpr (MODE == X_ADJ) {
         // inputs: components 0..5 the strain S (xx, xy, xz, yy, yz, zz),
         // 6..8 the velocity; a_i = 2 sum_j S_ij u_j, upper triangle (i, j)
@@ -320,7 +366,8 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
 }
 
 // ------------------------------------------------------------------ F3 pass
-template <class P, int T, int MODE, int SP, int W, typename R>
+// PRE = 1 issues the loads of component p + 1 before the transform of p.
+template <class P, int T, int MODE, int SP, int W, typename R, int PRE = 0>
 __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
 {
     constexpr int N = P::N, E = P::E;
@@ -346,13 +393,24 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
 #pragma unroll
         for (int i = 0; i < E; ++i) acc[j][i] = {0, 0};
 
-#pragma unroll 1
-    for (int p = 0; p < NC; ++p) {
-        cpx<R> v[E];
+    auto load = [&](int p, cpx<R>(&v)[E]) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int n = P::in_pos(g, i);
             v[i] = valid ? in[p * a.in_cs + (long long)n * a.MMx] : cpx<R>{0, 0};
+        }
+    };
+    cpx<R> nxt[PRE ? E : 1];
+    if constexpr (PRE) load(0, nxt);
+#pragma unroll 1
+    for (int p = 0; p < NC; ++p) {
+        cpx<R> v[E];
+        if constexpr (PRE) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) v[i] = nxt[i];
+            if (p + 1 < NC) load(p + 1, nxt);
+        } else {
+            load(p, v);
         }
         if constexpr (SP) P::template run<-1, T, 1>(v, g, reinterpret_cast<cpx<R>*>(reinterpret_cast<R*>(lds) + c), twl);
         else P::template run<-1, T, 0>(v, g, lds + c, twl);
@@ -537,26 +595,29 @@ hipError_t launch_col_p(const ColArgs& a, hipStream_t s)
                     tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len, s, a, done);
 }
 
-template <class PI, class PF, int U, int MODE, int W, typename R>
+template <class PI, class PF, int U, int MODE, int W, typename R, int BPC = 0>
 hipError_t launch_x(const XArgs& a, hipStream_t s)
 {
     constexpr int XL = x_line_len<PI, PF, R>();
     static_assert(PI::G * U <= 1024, "at most 1024 threads per block");
-    static_assert(sizeof(cpx<R>) * (XL * U + PI::tw_len + PF::tw_len) <= 163840, "LDS per block exceeds 160 KiB");
+    constexpr int TW = std::is_same<PI, PF>::value ? PI::tw_len : PI::tw_len + PF::tw_len;
+    static_assert(sizeof(cpx<R>) * (XL * U + TW) <= 163840, "LDS per block exceeds 160 KiB");
     static bool done = false;
     if (a.K != Cut<PI::N>::K) return hipErrorInvalidValue;
-    return launch_k(k_xline<PI, PF, U, MODE, W, R>, (a.nunits + U - 1) / U, PI::G * U,
-                    sizeof(cpx<R>) * (XL * U + PI::tw_len + PF::tw_len), s, a, done);
+    long long grid = (a.nunits + U - 1) / U;
+    if (BPC > 0 && grid > (long long)device_cus() * BPC) grid = (long long)device_cus() * BPC;
+    return launch_k(k_xline<PI, PF, U, MODE, W, R, BPC>, grid, PI::G * U,
+                    sizeof(cpx<R>) * (XL * U + TW), s, a, done);
 }
 
-template <class P, int T, int MODE, int SP, int W, typename R>
+template <class P, int T, int MODE, int SP, int W, typename R, int PRE = 0>
 hipError_t launch_f3(const F3Args& a, hipStream_t s)
 {
     static_assert(P::G * T <= 1024, "at most 1024 threads per block");
     static_assert(tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len <= 163840, "LDS per block exceeds 160 KiB");
     static bool done = false;
     if (!cut_ok<P::N>(a.K, a.M) || a.Mx != Cut<P::N>::K + 1) return hipErrorInvalidValue;
-    return launch_k(k_f3<P, T, MODE, SP, W, R>, (a.Q + T - 1) / T, P::G * T,
+    return launch_k(k_f3<P, T, MODE, SP, W, R, PRE>, (a.Q + T - 1) / T, P::G * T,
                     tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len, s, a, done);
 }
 

@@ -18,16 +18,16 @@ void add_col_p(SizeKernels& k, const char* name)
     add_variant(k.fwd, k.n_fwd, launch_col_p<P, T, -1, COL_FWD_TRUNC, SP, W, BPC, R>, name);
 }
 
-template <class PI, class PF, int U, int W, typename R>
+template <class PI, class PF, int U, int W, typename R, int BPC = 0>
 void add_x(SizeKernels& k, const char* name)
 {
-    add_variant(k.x, k.n_x, launch_x<PI, PF, U, X_RHS, W, R>, name);
+    add_variant(k.x, k.n_x, launch_x<PI, PF, U, X_RHS, W, R, BPC>, name);
 }
 
-template <class P, int T, int SP, int W, typename R>
+template <class P, int T, int SP, int W, typename R, int PRE = 0>
 void add_f3(SizeKernels& k, const char* name)
 {
-    add_variant(k.f3, k.n_f3, launch_f3<P, T, F3_RHS, SP, W, R>, name);
+    add_variant(k.f3, k.n_f3, launch_f3<P, T, F3_RHS, SP, W, R, PRE>, name);
 }
 
 template <class P, int T, int SP, int W, int BPC, typename R>
