@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
         tables();
     }
     static_assert(BPC == 0 || MODE == X_RHS, "persistent blocks are for the product pass");
-    const int tid = threadIdx.x, u = tid / G, t = tid % G;
+    const int tid = threadIdx.x, u = tid / G, t = tid % G, t0 = t;
     cpx<R>* my = reinterpret_cast<cpx<R>*>(smem_raw) + u * LL;
     long long samp = 0, l1 = 0;
     bool valid = false;
@@ -243,6 +243,11 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
 
     // forward (R2C) of v = a + i b; store k_x <= K of both lines as product p
     auto fwd_store = [&](int p, cpx<R>(&v)[E]) {
+        // an opaque copy of the thread index: the LDS addresses of each
+        // product's transform are recomputed rather than kept live across
+        // all six
+        int t = t0;
+        asm volatile("" : "+v"(t));
         PF::template run<-1, 1, 0, true>(v, t, my, twF);
 #pragma unroll
         for (int i = 0; i < E; ++i) my[PF::out_pos(t, i)] = v[i];
@@ -393,27 +398,32 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
 #pragma unroll
         for (int i = 0; i < E; ++i) acc[j][i] = {0, 0};
 
-    auto load = [&](int p, cpx<R>(&v)[E]) {
+    auto load = [&](int p, cpx<R>(&v)[E], int gg) {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
-            const int n = P::in_pos(g, i);
+            const int n = P::in_pos(gg, i);
             v[i] = valid ? in[p * a.in_cs + (long long)n * a.MMx] : cpx<R>{0, 0};
         }
     };
     cpx<R> nxt[PRE ? E : 1];
-    if constexpr (PRE) load(0, nxt);
+    if constexpr (PRE) load(0, nxt, g);
 #pragma unroll 1
     for (int p = 0; p < NC; ++p) {
+        // opaque copies of the thread coordinates: the addresses derived
+        // from them are recomputed per component instead of being hoisted
+        // out of the loop, which would hold them in registers throughout
+        int gg = g, cc = c;
+        asm volatile("" : "+v"(gg), "+v"(cc));
         cpx<R> v[E];
         if constexpr (PRE) {
 #pragma unroll
             for (int i = 0; i < E; ++i) v[i] = nxt[i];
-            if (p + 1 < NC) load(p + 1, nxt);
+            if (p + 1 < NC) load(p + 1, nxt, gg);
         } else {
-            load(p, v);
+            load(p, v, gg);
         }
-        if constexpr (SP) P::template run<-1, T, 1>(v, g, reinterpret_cast<cpx<R>*>(reinterpret_cast<R*>(lds) + c), twl);
-        else P::template run<-1, T, 0>(v, g, lds + c, twl);
+        if constexpr (SP) P::template run<-1, T, 1>(v, gg, reinterpret_cast<cpx<R>*>(reinterpret_cast<R*>(lds) + cc), twl);
+        else P::template run<-1, T, 0>(v, gg, lds + cc, twl);
         if constexpr (MODE == F3_RHS) {
             // component p = (i, j) of the upper triangle adds k_j B to b_i
             // and, off the diagonal, k_i B to b_j: b_r += (wxy_r + wz_r k_z) B
