@@ -2,10 +2,13 @@
 
 Default workload: the seeded perturbed shear layer at N = 1024^3, FP32, s = 1.5,
 step multiplier at m_N = N/3, eps_N = 1e-3 (32/N)^2, dt from CFL 0.5; W warm-up
-steps, then K timed steps (one ns_step call, graph replay), inputs resident in
-HBM.  Prints one JSON line with Mpts*RK-steps/s, the HBM roofline of the
-dominant pass (algorithmic bytes / live HIP-event duration) and the CPU
-oracle timed on a bounded sample of the same workload family.
+steps (graph replay), then K timed steps in one ns_step call, inputs resident
+in HBM.  The timed steps run with the pass profiler on: HIP events bracket
+every pass launch on the library's stream (eager launches; --no-profile
+times graph replays instead).  Prints one JSON line with Mpts*RK-steps/s,
+the HBM roofline of the dominant pass (algorithmic bytes / its average
+event-timed duration in the timed region) and the CPU oracle timed on a
+bounded sample of the same workload family.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 2] [--n 1024]
 """
@@ -132,16 +135,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, n: int):
+def measured_traffic(kernel: str, n: int, variant: str):
     """HBM bytes per launch of a pass from the committed rocprofv3 PMC
     summary (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel
-    calibration), or None if there is none or the kernels changed since."""
+    calibration), or None if there is none, the kernels changed since, or
+    the figure belongs to another schedule variant than the one timed."""
     path = os.path.join(PROFILE_DIR, "traffic_%s_n%d.json" % (kernel, n))
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_hash") != kernel_source_hash():
+    if d.get("source_hash") != kernel_source_hash() or d.get("variant") != variant:
         return None
     return d.get("bytes_per_launch")
 
@@ -206,6 +210,11 @@ def main():
 
     if args.warmup > 0:
         S.step(uh, dt, args.warmup)
+    # the per-pass HIP events are recorded on the library's stream inside the
+    # timed region itself (the profiler launches the passes eagerly instead
+    # of replaying the step graph)
+    if not args.no_profile:
+        S.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S.step(uh, dt, args.steps)
@@ -219,8 +228,6 @@ def main():
     roofline = None
     per_pass = {}
     if not args.no_profile:
-        S.profile(True)
-        S.step(uh, dt, args.steps)
         prof = S.profile_read()
         S.profile(False)
         bpl = perfmodel.pass_bytes_per_launch(n, rbytes)
@@ -230,7 +237,7 @@ def main():
                 per_pass[name] = {"avg_ms": avg, "launches": cnt, "GBps": bpl[name] / (avg * 1e-3) / 1e9}
         dom = max(per_pass, key=lambda k: per_pass[k]["avg_ms"] * per_pass[k]["launches"])
         ach = per_pass[dom]["GBps"]
-        traffic = measured_traffic(dom, n)
+        traffic = measured_traffic(dom, n, schedule.get(dom))
         roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                     "traffic": traffic, "kernel": dom, "algorithmic_bytes_per_launch": bpl[dom]}
     step_bytes = perfmodel.step_bytes(n, rbytes)
