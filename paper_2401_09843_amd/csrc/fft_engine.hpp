@@ -234,6 +234,24 @@ __device__ __forceinline__ int lds_pos(int pos) { return pos + pos / PD; }
 // stay inside one row.  The padding is a multiple of P and constant over
 // each block of D elements, so m P and the tile offsets stay immediate
 // address offsets.  Stages with P >= W write at unit stride and need none.
+constexpr bool pow2c(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// Period of the layout: lds_slot(x + c) = lds_slot(x) + lds_delta(c) for
+// every multiple c of it.
+template <int PD, int P, int R, int ES>
+constexpr int lds_period()
+{
+    constexpr int W = 256 / ES;
+    return PD > 0 ? PD : (P >= W ? 1 : (P * R > W ? P * R : W));
+}
+
+template <int PD, int P, int R, int ES>
+constexpr int lds_delta(int c)
+{
+    constexpr int W = 256 / ES;
+    return PD > 0 ? c + c / PD : (P >= W ? c : c + P * (c / lds_period<PD, P, R, ES>()));
+}
+
 template <int PD, int P, int R, int ES>
 __device__ __forceinline__ int lds_slot(int pos)
 {
@@ -265,22 +283,62 @@ struct Stages<N, G, DIR, PD, LS, SP, T, P, OFF, R, Rest...> {
     static constexpr int NB = N / (R * G);
     static_assert(NB * R * G == N, "G must divide N / R for every radix");
 
+    // Where the layout is additive over the constant parts of the indices,
+    // one slot per thread is computed and the rest are immediate offsets:
+    // writes go to (t - k) R + k + (q G R + m P) with k = t mod P when P
+    // divides G, and that offset never carries a row past a period boundary
+    // (k + m P < P R); reads go to t + (q G + m N / R2).
+    template <int ES>
+    static constexpr bool fast_write()
+    {
+        constexpr int PER = lds_period<PD, P, R, ES>();
+        if (G % P != 0 || (G * R) % PER != 0) return false;
+        if (PD > 0) return P == 1 ? R % PD == 0 : P % PD == 0;
+        return pow2c(P) && pow2c(R) && pow2c(PER);
+    }
+    template <int R2, int ES>
+    static constexpr bool fast_read()
+    {
+        constexpr int PER = lds_period<PD, P, R, ES>();
+        return G % PER == 0 && (N / R2) % PER == 0;
+    }
+
     template <int R2, typename L, typename Get, typename Put>
     __device__ __forceinline__ static void exchange(cpx<T> (&v)[E], int t, L* lds, Get get, Put put)
     {
+        constexpr int ES = sizeof(L);
+        if constexpr (fast_write<ES>()) {
+            const int k = t % P;
+            L* base = lds + lds_slot<PD, P, R, ES>((t - k) * R + k) * LS;
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            const int b = t + q * G;
-            const int k = b % P;
-            const int j = (b - k) * R + k;
+            for (int q = 0; q < NB; ++q)
 #pragma unroll
-            for (int m = 0; m < R; ++m) lds[lds_slot<PD, P, R, sizeof(L)>(j + m * P) * LS] = get(v[q * R + m]);
+                for (int m = 0; m < R; ++m) base[lds_delta<PD, P, R, ES>(q * G * R + m * P) * LS] = get(v[q * R + m]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int b = t + q * G;
+                const int k = b % P;
+                const int j = (b - k) * R + k;
+#pragma unroll
+                for (int m = 0; m < R; ++m) lds[lds_slot<PD, P, R, ES>(j + m * P) * LS] = get(v[q * R + m]);
+            }
         }
         __syncthreads();
+        if constexpr (fast_read<R2, ES>()) {
+            const L* base = lds + lds_slot<PD, P, R, ES>(t) * LS;
 #pragma unroll
-        for (int q = 0; q < N / (R2 * G); ++q)
+            for (int q = 0; q < N / (R2 * G); ++q)
 #pragma unroll
-            for (int m = 0; m < R2; ++m) put(v[q * R2 + m], lds[lds_slot<PD, P, R, sizeof(L)>(t + q * G + m * (N / R2)) * LS]);
+                for (int m = 0; m < R2; ++m)
+                    put(v[q * R2 + m], base[lds_delta<PD, P, R, ES>(q * G + m * (N / R2)) * LS]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < N / (R2 * G); ++q)
+#pragma unroll
+                for (int m = 0; m < R2; ++m)
+                    put(v[q * R2 + m], lds[lds_slot<PD, P, R, ES>(t + q * G + m * (N / R2)) * LS]);
+        }
         __syncthreads();
     }
 
