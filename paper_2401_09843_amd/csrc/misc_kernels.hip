@@ -186,6 +186,20 @@ __global__ void k_fill(double* p, double v, int n)
     if (i < n) p[i] = v;
 }
 
+// uniform values in [-1, 1) from a counter-based integer hash of the index
+// (SplitMix64 finaliser); used to give the autotuner realistic operands
+template <typename R>
+__global__ void k_fill_random(R* p, long long n, unsigned long long seed)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    unsigned long long z = seed + 0x9E3779B97F4A7C15ULL * (unsigned long long)(i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    p[i] = (R)((double)(z >> 11) * (1.0 / 4503599627370496.0) - 1.0);
+}
+
 inline unsigned nblocks(long long total, int threads) { return (unsigned)((total + threads - 1) / threads); }
 
 }  // namespace
@@ -224,6 +238,14 @@ hipError_t launch_spectrum(bool f64, const void* u, double* E, int N, int K, int
     int nb = kbins < kmax ? kbins : kmax;
     if (f64) hipLaunchKernelGGL(k_spectrum<double>, dim3(nb), dim3(SPEC_THREADS), 0, s, (const cpx<double>*)u, E, N, K, kbins);
     else hipLaunchKernelGGL(k_spectrum<float>, dim3(nb), dim3(SPEC_THREADS), 0, s, (const cpx<float>*)u, E, N, K, kbins);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_random(bool f64, void* p, long long nreal, unsigned long long seed, hipStream_t s)
+{
+    if (nreal <= 0) return hipSuccess;
+    if (f64) hipLaunchKernelGGL(k_fill_random<double>, dim3(nblocks(nreal, 256)), dim3(256), 0, s, (double*)p, nreal, seed);
+    else hipLaunchKernelGGL(k_fill_random<float>, dim3(nblocks(nreal, 256)), dim3(256), 0, s, (float*)p, nreal, seed);
     return hipGetLastError();
 }
 

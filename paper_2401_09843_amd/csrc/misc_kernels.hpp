@@ -8,5 +8,6 @@ hipError_t launch_unpack(bool f64, const void* compact, void* r2c, int N, int K,
 hipError_t launch_project(bool f64, void* r2c, int N, int K, hipStream_t s);
 hipError_t launch_spectrum(bool f64, const void* r2c, double* E, int N, int K, int kbins, hipStream_t s);
 hipError_t launch_fill(double* p, double v, int n, hipStream_t s);
+hipError_t launch_fill_random(bool f64, void* p, long long nreal, unsigned long long seed, hipStream_t s);
 hipError_t launch_strain(bool f64, const void* lam, void* S, int K, long long batch, hipStream_t s);
 }  // namespace ns

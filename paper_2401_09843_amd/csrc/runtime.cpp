@@ -568,11 +568,14 @@ ns_status tune_group(ns_ctx* c, Group& g)
     const char* path = c->tune_cache.empty() ? nullptr : c->tune_cache.c_str();
     if (path && !key.empty() && load_tuning(c, g, path, key)) return NS_OK;
     const size_t cw = cwb(c);
-    HIP_TRY(c, hipMemsetAsync(g.U0, 0, cw * g.st * g.B, c->stream));
-    HIP_TRY(c, hipMemsetAsync(g.U1, 0, cw * g.st * g.B, c->stream));
-    HIP_TRY(c, hipMemsetAsync(g.A, 0, cw * 6ULL * g.N * g.MMx * g.B, c->stream));
-    HIP_TRY(c, hipMemsetAsync(g.Bw, 0, cw * 3ULL * g.N * g.N * g.Mx * g.B, c->stream));
-    HIP_TRY(c, hipMemsetAsync(g.C, 0, cw * 6ULL * g.N * g.N * g.Mx * g.B, c->stream));
+    // the variants are timed on seeded values in [-1, 1) rather than zeros:
+    // the x pass draws more power, and runs slower, on realistic data
+    const long long per = (long long)(cw / (c->f64 ? 8 : 4));  // reals per complex word
+    HIP_TRY(c, launch_fill_random(c->f64, g.U0, per * (long long)g.st * g.B, 1, c->stream));
+    HIP_TRY(c, launch_fill_random(c->f64, g.U1, per * (long long)g.st * g.B, 2, c->stream));
+    HIP_TRY(c, launch_fill_random(c->f64, g.A, per * 6LL * g.N * g.MMx * g.B, 3, c->stream));
+    HIP_TRY(c, launch_fill_random(c->f64, g.Bw, per * 3LL * g.N * g.N * g.Mx * g.B, 4, c->stream));
+    HIP_TRY(c, launch_fill_random(c->f64, g.C, per * 6LL * g.N * g.N * g.Mx * g.B, 5, c->stream));
     const PassArgs a = pass_args(g, g.U0, g.U1, g.U0, 0.75, 0.25, 0.25, g.ones);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(c, hipEventCreate(&e0));
