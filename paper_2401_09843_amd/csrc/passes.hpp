@@ -238,6 +238,8 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
     };
     auto load_inv = [&](int c, cpx<R>(&v)[E]) {
         load_raw(c, v);
+        int t = t0;
+        asm volatile("" : "+v"(t));
         PI::template run<+1, 1, 0, true>(v, t, my, twI);
     };
 
@@ -372,7 +374,9 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
 
 // ------------------------------------------------------------------ F3 pass
 // PRE = 1 issues the loads of component p + 1 before the transform of p.
-template <class P, int T, int MODE, int SP, int W, typename R, int PRE = 0>
+// OB = 1 (F3_RHS): write the projected b-hat to a.scratch (state layout)
+// and leave hyperviscosity and the RK stage combination to k_rk_combine.
+template <class P, int T, int MODE, int SP, int W, typename R, int PRE = 0, int OB = 0>
 __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
 {
     constexpr int N = P::N, E = P::E;
@@ -429,7 +433,10 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
 #pragma unroll
         for (int i = 0; i < E; ++i) acc[j][i] = {0, 0};
 
-#pragma unroll 1
+    // the three-component modes unroll the loop: a runtime component index
+    // would turn the assignment into acc[p] and push acc to scratch memory
+    constexpr int UNR = MODE == F3_RHS ? 1 : NC;
+#pragma unroll UNR
     for (int p = 0; p < NC; ++p) {
         // opaque copies of the thread coordinates: the addresses derived
         // from them are recomputed per component instead of being hoisted
@@ -541,7 +548,11 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
                 b[j].y -= kv[j] * kb.y * inv;
             }
         }
-        if constexpr (MODE == F3_RHS) {
+        if constexpr (MODE == F3_RHS && OB) {
+            cpx<R>* o = static_cast<cpx<R>*>(a.scratch) + st;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) o[j * a.st_cs] = b[j];
+        } else if constexpr (MODE == F3_RHS) {
             const R rt = rate[k2];
             const R ca = (R)a.ca, cb = (R)a.cb, cdt = (R)(a.cc * dts);
             const cpx<R>* us = static_cast<const cpx<R>*>(a.us) + st;
@@ -648,7 +659,7 @@ hipError_t launch_x(const XArgs& a, hipStream_t s)
                     sizeof(cpx<R>) * (XL * U + TW), s, a, done);
 }
 
-template <class P, int T, int MODE, int SP, int W, typename R, int PRE = 0>
+template <class P, int T, int MODE, int SP, int W, typename R, int PRE = 0, int OB = 0>
 hipError_t launch_f3(const F3Args& a, hipStream_t s)
 {
     static_assert(P::G * T <= 1024, "at most 1024 threads per block");
@@ -661,7 +672,7 @@ hipError_t launch_f3(const F3Args& a, hipStream_t s)
         const long long cap = (long long)device_cus() * (P::G * T >= 1024 ? 1 : 2);
         if (grid > cap) grid = cap;
     }
-    return launch_k(k_f3<P, T, MODE, SP, W, R, PRE>, grid, P::G * T,
+    return launch_k(k_f3<P, T, MODE, SP, W, R, PRE, OB>, grid, P::G * T,
                     tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len, s, a, done);
 }
 
@@ -742,6 +753,54 @@ hipError_t launch_f3_split(const F3Args& a, hipStream_t s)
     if (e != hipSuccess) return e;
     const long long total = B * MM;
     hipLaunchKernelGGL(k_f3_epilogue<R>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// Second half of the contracted F3 schedule: per retained mode,
+// out = ca u0 + cb us + cc dt (b - rate us) with the projected b-hat from
+// a.scratch, one thread per mode and sample.
+template <typename R>
+__global__ void __launch_bounds__(256) k_rk_combine(F3Args a)
+{
+    const long long per = (long long)a.M * a.MMx;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long B = a.Q / a.MMx;
+    if (idx >= B * per) return;
+    const long long samp = idx / per, m = idx % per;
+    const int jz = (int)(m / a.MMx), s = (int)(m % a.MMx);
+    const int K = a.K, M = a.M;
+    const int jy = s / a.Mx, kxi = s % a.Mx;
+    const int kyi = jy <= K ? jy : jy - M, kzi = jz <= K ? jz : jz - M;
+    const int k2 = kxi * kxi + kyi * kyi + kzi * kzi;
+    const R rt = static_cast<const R*>(a.rate)[k2];
+    const R ca = (R)a.ca, cb = (R)a.cb, cdt = (R)(a.cc * a.dt[samp]);
+    const long long st = samp * a.st_ss + m;
+    const cpx<R>* bh = static_cast<const cpx<R>*>(a.scratch) + st;
+    const cpx<R>* us = static_cast<const cpx<R>*>(a.us) + st;
+    const cpx<R>* u0 = static_cast<const cpx<R>*>(a.u0) + st;
+    cpx<R>* o = static_cast<cpx<R>*>(a.out) + st;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const cpx<R> w = us[j * a.st_cs], b = bh[j * a.st_cs];
+        cpx<R> r = {cb * w.x + cdt * (b.x - rt * w.x), cb * w.y + cdt * (b.y - rt * w.y)};
+        if (a.ca != 0.0) {
+            const cpx<R> w0 = u0[j * a.st_cs];
+            r.x += ca * w0.x;
+            r.y += ca * w0.y;
+        }
+        o[j * a.st_cs] = r;
+    }
+}
+
+// Contracted F3 schedule: the fused z pass writes the projected b-hat (three
+// components instead of six), then the pointwise RK combination.
+template <class P, int T, int SP, int W, typename R, int PRE>
+hipError_t launch_f3_ob(const F3Args& a, hipStream_t s)
+{
+    hipError_t e = launch_f3<P, T, F3_RHS, SP, W, R, PRE, 1>(a, s);
+    if (e != hipSuccess) return e;
+    const long long total = (a.Q / a.MMx) * (long long)a.M * a.MMx;
+    hipLaunchKernelGGL(k_rk_combine<R>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

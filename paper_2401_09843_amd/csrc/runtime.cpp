@@ -440,23 +440,25 @@ ns_status run_vjp(ns_ctx* c, Group& g, const void* u, const void* lam, void* out
     hipStream_t s = c->stream;
     const size_t cw = cwb(c);
     HIP_TRY(c, launch_strain(c->f64, lam, g.Sb, g.K, B, s));
+    // the column passes use the schedules chosen for the forward I1, I2, F2
+    const auto zinv = k->inv[g.sel[0]].fn, yinv = k->inv[g.sel[1]].fn, yfwd = k->fwd[g.sel[3]].fn;
     // z: strain [B][6][M][MMx] and velocity [B][3][M][MMx] -> [B][9][N][MMx]
     ColArgs s1{g.Sb, g.A9, g.tw, B * 6 * MMx, MMx, 6, M * MMx, 6 * M * MMx, N * MMx, 9 * N * MMx, g.K, g.M, 1.0};
-    HIP_TRY(c, k->inv[0].fn(s1, s));
+    HIP_TRY(c, zinv(s1, s));
     ColArgs u1{u, (char*)g.A9 + cw * 6 * N * MMx, g.tw, B * 3 * MMx, MMx, 3, M * MMx, 3 * M * MMx, N * MMx,
                9 * N * MMx, g.K, g.M, 1.0};
-    HIP_TRY(c, k->inv[0].fn(u1, s));
+    HIP_TRY(c, zinv(u1, s));
     // y: [B][9N][M][Mx] -> [B][9N][N][Mx]
     ColArgs y1{g.A9, g.B9, g.tw, B * 9 * N * Mx, Mx, 9 * N, M * Mx, 9 * N * M * Mx, N * Mx, 9 * N * N * Mx,
                g.K, g.M, 1.0};
-    HIP_TRY(c, k->inv[0].fn(y1, s));
+    HIP_TRY(c, yinv(y1, s));
     // x: a = 2 S u -> [B][3][N*N][Mx]
     XArgs ax{g.B9, g.C, g.tw, B * N * N / 2, N * N * Mx, N * N * Mx, 9 * N * N * Mx, 3 * N * N * Mx, g.K, 1.0 / N};
     HIP_TRY(c, k->x_adj(ax, s));
     // y forward: [B][3N][N][Mx] -> [B][3N][M][Mx]
     ColArgs y2{g.C, g.A, g.tw, B * 3 * N * Mx, Mx, 3 * N, N * Mx, 3 * N * N * Mx, M * Mx, 3 * N * M * Mx,
                g.K, g.M, 1.0 / N};
-    HIP_TRY(c, k->fwd[0].fn(y2, s));
+    HIP_TRY(c, yfwd(y2, s));
     // z forward + adjoint stage epilogue
     F3Args f{g.A, g.L3, lam, out, g.tw, g.rate, dt, B * MMx, (int)MMx, g.Mx, g.K, g.M,
              3 * N * MMx, N * MMx, g.st, M * MMx, c3, 0.0, cc, 1.0 / N, g.L2, g.L1, c2, c1, nullptr};
@@ -901,7 +903,7 @@ ns_status ns_forward(ns_ctx* c, const void* const* u, void* const* uh)
         // y: [3N][N][Mx] -> [3N][M][Mx]
         ColArgs a{g.C, g.A, g.tw, 3 * N * Mx, Mx, 3 * N, N * Mx, 3 * N * N * Mx, M * Mx, 3 * N * M * Mx,
                   g.K, g.M, 1.0 / N};
-        HIP_TRY(c, g.kern->fwd[0].fn(a, s));
+        HIP_TRY(c, g.kern->fwd[g.sel[3]].fn(a, s));
         // z + T + Leray: [3][N][MMx] -> compact [3][M][MMx]
         F3Args f{g.A, nullptr, nullptr, g.U1, g.tw, g.rate, g.ones, MMx, (int)MMx, g.Mx, g.K, g.M,
                  0, N * MMx, 0, M * MMx, 0.0, 0.0, 0.0, 1.0 / N, nullptr, nullptr, 0.0, 0.0, nullptr};
@@ -922,10 +924,10 @@ ns_status ns_inverse(ns_ctx* c, const void* const* uh, void* const* u)
         hipStream_t s = c->stream;
         HIP_TRY(c, launch_pack(c->f64, uh[i], g.U1, g.N, g.K, s));
         ColArgs a1{g.U1, g.A, g.tw, 3 * MMx, MMx, 3, M * MMx, 3 * M * MMx, N * MMx, 3 * N * MMx, g.K, g.M, 1.0};
-        HIP_TRY(c, g.kern->inv[0].fn(a1, s));
+        HIP_TRY(c, g.kern->inv[g.sel[0]].fn(a1, s));
         ColArgs a2{g.A, g.Bw, g.tw, 3 * N * Mx, Mx, 3 * N, M * Mx, 3 * N * M * Mx, N * Mx, 3 * N * N * Mx,
                    g.K, g.M, 1.0};
-        HIP_TRY(c, g.kern->inv[0].fn(a2, s));
+        HIP_TRY(c, g.kern->inv[g.sel[1]].fn(a2, s));
         XArgs ax{g.Bw, u[i], g.tw, N * N / 2, N * N * Mx, N * N * N, 0, 0, g.K, 1.0};
         HIP_TRY(c, g.kern->x_inv3(ax, s));
     }

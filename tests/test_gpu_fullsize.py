@@ -100,3 +100,28 @@ def test_helical_decay_full_size(ns, n):
     err = float(torch.linalg.vector_norm(uh - R ** steps * ref).item() / torch.linalg.vector_norm(R ** steps * ref).item())
     print("n=%d helical decay rel err %.3e (R^n = %.4f)" % (n, err, R ** steps), flush=True)
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("n,steps", [(256, 100), (512, 20), (1024, 20)])
+def test_fp32_against_fp64_shear_layer(ns, n, steps):
+    """The seed-0 shear layer of the benchmark family: the FP32 solver
+    after `steps` SSP-RK3 steps against the FP64 solver (itself checked
+    against the oracle per right-hand side), same initial spectrum and dt.
+    Relative velocity L2 over the spectrum <= 1e-3; the value is printed."""
+    print("fp32 vs fp64 shear n=%d steps=%d" % (n, steps), flush=True)
+    u0, _, _ = inputs.shear_layer_torch(n, seed=0, device="cuda", dtype=torch.float64)
+    dt = float(0.5 * (2 * np.pi / n) / u0.abs().sum(dim=0).max().item())
+    S64 = ns.Solver(n, dtype=torch.float64, tune=False)
+    uh64 = S64.forward(u0)
+    del u0
+    uh32 = uh64.to(torch.complex64)
+    S64.step(uh64, dt, steps)
+    del S64
+    torch.cuda.empty_cache()
+    S32 = ns.Solver(n, dtype=torch.float32, tune=False)
+    S32.step(uh32, dt, steps)
+    del S32
+    err = float(torch.linalg.vector_norm(uh32.to(torch.complex128) - uh64).item()
+                / torch.linalg.vector_norm(uh64).item())
+    print("n=%d: FP32 vs FP64 after %d steps, relative L2 %.3e" % (n, steps, err), flush=True)
+    assert err <= 1e-3
