@@ -439,8 +439,10 @@ struct Plan<N_, G_, Radices<Rs...>> {
     {
 #pragma unroll
         for (int j = 0; j < tw_per_thread<NT>; ++j) {
+            // branch-free (entry 0 stands in past the end), so that r stays
+            // in registers
             const int i = threadIdx.x + j * NT;
-            if (i < tw_len) r[j] = src[TwTable<N_, 1, Rs...>::src_index(i)];
+            r[j] = src[i < tw_len ? TwTable<N_, 1, Rs...>::src_index(i) : 0];
         }
     }
     template <int NT, typename T>

@@ -192,7 +192,9 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
     constexpr int NT = G * U;
     cpx<R> ti[PI::template tw_per_thread<NT> > 0 ? PI::template tw_per_thread<NT> : 1];
     cpx<R> tf[PF::template tw_per_thread<NT> > 0 ? PF::template tw_per_thread<NT> : 1];
-    if constexpr (MODE == X_RHS && BPC == 0) {
+    // (FP32 only: the FP64 build keeps the staged entries in scratch memory)
+    constexpr bool STAGE = MODE == X_RHS && BPC == 0 && sizeof(R) == 4;
+    if constexpr (STAGE) {
         PI::template fetch_tw<NT>(ti, static_cast<const cpx<R>*>(a.tw));
         if constexpr (!SAME) PF::template fetch_tw<NT>(tf, static_cast<const cpx<R>*>(a.tw));
     } else {
@@ -275,7 +277,7 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
         load_raw(0, z0);
         load_raw(1, z1);
         load_raw(2, z2);
-        if constexpr (BPC == 0) {
+        if constexpr (STAGE) {
             PI::template put_tw<NT>(twI, ti);
             if constexpr (!SAME) PF::template put_tw<NT>(twF, tf);
             __syncthreads();
