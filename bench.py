@@ -99,7 +99,7 @@ def run_ensemble(args):
     mean64 = spec[64:].mean(0).cpu().tolist()
     out = {
         "metric": "ensemble samples/s (96 samples: 64x128^3 + 32x64^3, 200 SSP-RK3 steps)",
-        "value": len(sizes) / t_batched * (200.0 / steps),
+        "value": len(sizes) / (t_batched * 200.0 / steps),
         "unit": "samples/s",
         "n_gpus": 1,
         "steps": steps,
@@ -111,7 +111,7 @@ def run_ensemble(args):
         "dtype": "f32",
         "data": "synthetic: seeded shear layers, seeds 1000+i, delta ~ U[0.01,0.05]",
         "config": {"workload": "ensemble 64x128^3 + 32x64^3 FP32", "parallelism": "single GPU"},
-        "looped_plain_samples_per_s": len(sizes) / t_loop * (200.0 / steps),
+        "looped_plain_samples_per_s": len(sizes) / (t_loop * 200.0 / steps),
         "speedup_vs_loop": t_loop / t_batched,
         "max_rel_diff_batched_vs_loop": worst,
         "mean_E_k_128": mean128[:44],
@@ -153,7 +153,7 @@ def measured_traffic(kernel: str, n: int, variant: str):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20; 200 with --ensemble)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--dtype", default="fp32", choices=["fp32", "fp64"])
@@ -185,6 +185,8 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_read": src.numel() * 4, "bytes_written": dst.numel() * 4, "launches": 3}))
         return
 
+    if args.steps is None:
+        args.steps = 200 if args.ensemble else 20
     if args.ensemble:
         run_ensemble(args)
         return
