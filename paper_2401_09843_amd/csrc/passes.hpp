@@ -247,11 +247,6 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
 
     // forward (R2C) of v = a + i b; store k_x <= K of both lines as product p
     auto fwd_store = [&](int p, cpx<R>(&v)[E]) {
-        // an opaque copy of the thread index: the LDS addresses of each
-        // product's transform are recomputed rather than kept live across
-        // all six
-        int t = t0;
-        asm volatile("" : "+v"(t));
         PF::template run<-1, 1, 0, true>(v, t, my, twF);
 #pragma unroll
         for (int i = 0; i < E; ++i) my[PF::out_pos(t, i)] = v[i];
