@@ -58,9 +58,6 @@ struct F3Args {
     const void* l2;
     const void* l1;
     double c2, c1;
-    // scratch for schedules that stage the truncated z transform in HBM
-    // (at least 6 M M Mx complex per sample)
-    void* scratch;
 };
 
 // Schedule variants of the tuned passes.

@@ -371,9 +371,7 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
 
 // ------------------------------------------------------------------ F3 pass
 // PRE = 1 issues the loads of component p + 1 before the transform of p.
-// OB = 1 (F3_RHS): write the projected b-hat to a.scratch (state layout)
-// and leave hyperviscosity and the RK stage combination to k_rk_combine.
-template <class P, int T, int MODE, int SP, int W, typename R, int PRE = 0, int OB = 0>
+template <class P, int T, int MODE, int SP, int W, typename R, int PRE = 0>
 __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
 {
     constexpr int N = P::N, E = P::E;
@@ -545,11 +543,7 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
                 b[j].y -= kv[j] * kb.y * inv;
             }
         }
-        if constexpr (MODE == F3_RHS && OB) {
-            cpx<R>* o = static_cast<cpx<R>*>(a.scratch) + st;
-#pragma unroll
-            for (int j = 0; j < 3; ++j) o[j * a.st_cs] = b[j];
-        } else if constexpr (MODE == F3_RHS) {
+        if constexpr (MODE == F3_RHS) {
             const R rt = rate[k2];
             const R ca = (R)a.ca, cb = (R)a.cb, cdt = (R)(a.cc * dts);
             const cpx<R>* us = static_cast<const cpx<R>*>(a.us) + st;
@@ -656,7 +650,7 @@ hipError_t launch_x(const XArgs& a, hipStream_t s)
                     sizeof(cpx<R>) * (XL * U + TW), s, a, done);
 }
 
-template <class P, int T, int MODE, int SP, int W, typename R, int PRE = 0, int OB = 0>
+template <class P, int T, int MODE, int SP, int W, typename R, int PRE = 0>
 hipError_t launch_f3(const F3Args& a, hipStream_t s)
 {
     static_assert(P::G * T <= 1024, "at most 1024 threads per block");
@@ -669,136 +663,8 @@ hipError_t launch_f3(const F3Args& a, hipStream_t s)
         const long long cap = (long long)device_cus() * (P::G * T >= 1024 ? 1 : 2);
         if (grid > cap) grid = cap;
     }
-    return launch_k(k_f3<P, T, MODE, SP, W, R, PRE, OB>, grid, P::G * T,
+    return launch_k(k_f3<P, T, MODE, SP, W, R, PRE>, grid, P::G * T,
                     tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len, s, a, done);
-}
-
-// Epilogue of the split F3 schedule: the six truncated, scaled components
-// B-hat (compact, [B][6][M][MMx] in a.scratch) -> b = -i sum_j k_j B_ij,
-// Leray projection, hyperviscosity and the SSP-RK3 stage combination, one
-// thread per retained mode.
-template <typename R>
-__global__ void __launch_bounds__(256) k_f3_epilogue(F3Args a)
-{
-    const long long per = (long long)a.M * a.MMx;
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long B = a.Q / a.MMx;
-    if (idx >= B * per) return;
-    const long long samp = idx / per, m = idx % per;
-    const int jz = (int)(m / a.MMx), s = (int)(m % a.MMx);
-    const int K = a.K, M = a.M;
-    const int jy = s / a.Mx, kxi = s % a.Mx;
-    const int kyi = jy <= K ? jy : jy - M, kzi = jz <= K ? jz : jz - M;
-    const R kv[3] = {(R)kxi, (R)kyi, (R)kzi};
-    const cpx<R>* Bh = static_cast<const cpx<R>*>(a.scratch) + samp * 6 * per + m;
-    cpx<R> Bv[6];
-#pragma unroll
-    for (int p = 0; p < 6; ++p) Bv[p] = Bh[p * per];
-    // b_i = -i sum_j k_j B_ij over the upper-triangle storage
-    const int tri[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
-    cpx<R> b[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        R sx = 0, sy = 0;
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            sx += kv[j] * Bv[tri[i][j]].x;
-            sy += kv[j] * Bv[tri[i][j]].y;
-        }
-        b[i] = {sy, -sx};
-    }
-    const int k2 = kxi * kxi + kyi * kyi + kzi * kzi;
-    if (k2 > 0) {
-        const R inv = (R)1 / (R)k2;
-        const R bx = (kv[0] * b[0].x + kv[1] * b[1].x + kv[2] * b[2].x) * inv;
-        const R by = (kv[0] * b[0].y + kv[1] * b[1].y + kv[2] * b[2].y) * inv;
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            b[j].x -= kv[j] * bx;
-            b[j].y -= kv[j] * by;
-        }
-    }
-    const R rt = static_cast<const R*>(a.rate)[k2];
-    const R ca = (R)a.ca, cb = (R)a.cb, cdt = (R)(a.cc * a.dt[samp]);
-    const long long st = samp * a.st_ss + (long long)jz * a.MMx + s;
-    const cpx<R>* us = static_cast<const cpx<R>*>(a.us) + st;
-    const cpx<R>* u0 = static_cast<const cpx<R>*>(a.u0) + st;
-    cpx<R>* o = static_cast<cpx<R>*>(a.out) + st;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const cpx<R> w = us[j * a.st_cs];
-        const cpx<R> f = {b[j].x - rt * w.x, b[j].y - rt * w.y};
-        cpx<R> r = {cb * w.x + cdt * f.x, cb * w.y + cdt * f.y};
-        if (a.ca != 0.0) {
-            const cpx<R> w0 = u0[j * a.st_cs];
-            r.x += ca * w0.x;
-            r.y += ca * w0.y;
-        }
-        o[j * a.st_cs] = r;
-    }
-}
-
-// Split F3 schedule: forward z of the six components with truncation into
-// scratch (a column pass), then the pointwise epilogue.
-template <class P, int T, int SP, int W, int BPC, typename R>
-hipError_t launch_f3_split(const F3Args& a, hipStream_t s)
-{
-    const long long B = a.Q / a.MMx, MM = (long long)a.M * a.MMx;
-    ColArgs c{a.in, a.scratch, a.tw, a.Q * 6, a.MMx, 6, a.in_cs, a.in_ss, MM, 6 * MM, a.K, a.M, a.scale};
-    hipError_t e = BPC > 0 ? launch_col_p<P, T, -1, COL_FWD_TRUNC, SP, W, (BPC > 0 ? BPC : 1), R>(c, s)
-                           : launch_col<P, T, -1, COL_FWD_TRUNC, SP, W, R>(c, s);
-    if (e != hipSuccess) return e;
-    const long long total = B * MM;
-    hipLaunchKernelGGL(k_f3_epilogue<R>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-// Second half of the contracted F3 schedule: per retained mode,
-// out = ca u0 + cb us + cc dt (b - rate us) with the projected b-hat from
-// a.scratch, one thread per mode and sample.
-template <typename R>
-__global__ void __launch_bounds__(256) k_rk_combine(F3Args a)
-{
-    const long long per = (long long)a.M * a.MMx;
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long B = a.Q / a.MMx;
-    if (idx >= B * per) return;
-    const long long samp = idx / per, m = idx % per;
-    const int jz = (int)(m / a.MMx), s = (int)(m % a.MMx);
-    const int K = a.K, M = a.M;
-    const int jy = s / a.Mx, kxi = s % a.Mx;
-    const int kyi = jy <= K ? jy : jy - M, kzi = jz <= K ? jz : jz - M;
-    const int k2 = kxi * kxi + kyi * kyi + kzi * kzi;
-    const R rt = static_cast<const R*>(a.rate)[k2];
-    const R ca = (R)a.ca, cb = (R)a.cb, cdt = (R)(a.cc * a.dt[samp]);
-    const long long st = samp * a.st_ss + m;
-    const cpx<R>* bh = static_cast<const cpx<R>*>(a.scratch) + st;
-    const cpx<R>* us = static_cast<const cpx<R>*>(a.us) + st;
-    const cpx<R>* u0 = static_cast<const cpx<R>*>(a.u0) + st;
-    cpx<R>* o = static_cast<cpx<R>*>(a.out) + st;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const cpx<R> w = us[j * a.st_cs], b = bh[j * a.st_cs];
-        cpx<R> r = {cb * w.x + cdt * (b.x - rt * w.x), cb * w.y + cdt * (b.y - rt * w.y)};
-        if (a.ca != 0.0) {
-            const cpx<R> w0 = u0[j * a.st_cs];
-            r.x += ca * w0.x;
-            r.y += ca * w0.y;
-        }
-        o[j * a.st_cs] = r;
-    }
-}
-
-// Contracted F3 schedule: the fused z pass writes the projected b-hat (three
-// components instead of six), then the pointwise RK combination.
-template <class P, int T, int SP, int W, typename R, int PRE>
-hipError_t launch_f3_ob(const F3Args& a, hipStream_t s)
-{
-    hipError_t e = launch_f3<P, T, F3_RHS, SP, W, R, PRE, 1>(a, s);
-    if (e != hipSuccess) return e;
-    const long long total = (a.Q / a.MMx) * (long long)a.M * a.MMx;
-    hipLaunchKernelGGL(k_rk_combine<R>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
-    return hipGetLastError();
 }
 
 template <class V, class F>

@@ -313,7 +313,7 @@ PassArgs pass_args(const Group& g, const void* us, void* out, const void* u0, do
                    g.K, g.M, 1.0 / N};
     // F3: [B][6][N][MMx] -> compact [B][3][M][MMx]
     a.f3 = F3Args{g.A, u0, us, out, g.tw, g.rate, dt, B * MMx, (int)MMx, g.Mx, g.K, g.M,
-                  6 * N * MMx, N * MMx, g.st, M * MMx, ca, cb, cc, 1.0 / N, nullptr, nullptr, 0.0, 0.0, g.Bw};
+                  6 * N * MMx, N * MMx, g.st, M * MMx, ca, cb, cc, 1.0 / N, nullptr, nullptr, 0.0, 0.0};
     return a;
 }
 
@@ -461,7 +461,7 @@ ns_status run_vjp(ns_ctx* c, Group& g, const void* u, const void* lam, void* out
     HIP_TRY(c, yfwd(y2, s));
     // z forward + adjoint stage epilogue
     F3Args f{g.A, g.L3, lam, out, g.tw, g.rate, dt, B * MMx, (int)MMx, g.Mx, g.K, g.M,
-             3 * N * MMx, N * MMx, g.st, M * MMx, c3, 0.0, cc, 1.0 / N, g.L2, g.L1, c2, c1, nullptr};
+             3 * N * MMx, N * MMx, g.st, M * MMx, c3, 0.0, cc, 1.0 / N, g.L2, g.L1, c2, c1};
     HIP_TRY(c, k->f3_adj(f, s));
     return NS_OK;
 }
@@ -906,7 +906,7 @@ ns_status ns_forward(ns_ctx* c, const void* const* u, void* const* uh)
         HIP_TRY(c, g.kern->fwd[g.sel[3]].fn(a, s));
         // z + T + Leray: [3][N][MMx] -> compact [3][M][MMx]
         F3Args f{g.A, nullptr, nullptr, g.U1, g.tw, g.rate, g.ones, MMx, (int)MMx, g.Mx, g.K, g.M,
-                 0, N * MMx, 0, M * MMx, 0.0, 0.0, 0.0, 1.0 / N, nullptr, nullptr, 0.0, 0.0, nullptr};
+                 0, N * MMx, 0, M * MMx, 0.0, 0.0, 0.0, 1.0 / N, nullptr, nullptr, 0.0, 0.0};
         HIP_TRY(c, g.kern->f3_proj(f, s));
         HIP_TRY(c, launch_unpack(c->f64, g.U1, uh[i], g.N, g.K, s));
     }

@@ -37,12 +37,7 @@ SizeKernels make32()
     add_f3<PB, 8, 1, 1, R>(k, "G128 r8.8.4.4 T8 split");
     add_f3<PB, 8, 1, 1, R, 1>(k, "G128 r8.8.4.4 T8 split prefetch");
     add_f3<PC, 8, 1, 1, R>(k, "G64 r16.16.4 T8 split");
-    add_f3_ob<PB, 8, 1, 1, R, 1>(k, "contracted: G128 r8.8.4.4 T8 split prefetch + RK");
-    add_f3_ob<PB, 4, 1, 1, R, 1>(k, "contracted: G128 r8.8.4.4 T4 split prefetch + RK");
     add_f3<PD, 4, 0, 1, R, 1>(k, "G256 r4.4.4.4.4 T4 prefetch");
-    add_f3_split<PA, 16, 1, 1, 0, R>(k, "split: G64 r16.16.4 T16 split + epilogue");
-    add_f3_split<PA, 8, 0, 1, 2, R>(k, "split: persistent G64 r16.16.4 T8 x2 + epilogue");
-    add_f3_split<PB, 8, 1, 1, 2, R>(k, "split: persistent G128 r8.8.4.4 T8 split x2 + epilogue");
     return k;
 }
 

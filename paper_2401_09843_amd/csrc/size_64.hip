@@ -22,7 +22,6 @@ SizeKernels make32()
     add_f3<PA, 8, 0, 1, R>(k, "G8 r8.8 T8");
     add_f3<PA, 32, 0, 1, R>(k, "G8 r8.8 T32");
     add_f3<PB, 8, 0, 1, R>(k, "G16 r4.4.4 T8");
-    add_f3_split<PA, 16, 0, 1, 0, R>(k, "split: G8 r8.8 T16 + epilogue");
     return k;
 }
 

@@ -30,16 +30,4 @@ void add_f3(SizeKernels& k, const char* name)
     add_variant(k.f3, k.n_f3, launch_f3<P, T, F3_RHS, SP, W, R, PRE>, name);
 }
 
-template <class P, int T, int SP, int W, typename R, int PRE>
-void add_f3_ob(SizeKernels& k, const char* name)
-{
-    add_variant(k.f3, k.n_f3, launch_f3_ob<P, T, SP, W, R, PRE>, name);
-}
-
-template <class P, int T, int SP, int W, int BPC, typename R>
-void add_f3_split(SizeKernels& k, const char* name)
-{
-    add_variant(k.f3, k.n_f3, launch_f3_split<P, T, SP, W, BPC, R>, name);
-}
-
 }  // namespace ns
