@@ -382,42 +382,20 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
     P::template load_tw<R>(twl, static_cast<const cpx<R>*>(a.tw));
     const int tid = threadIdx.x, c = tid % T, g = tid / T;
     constexpr int K = Cut<N>::K, M = Cut<N>::M, Mx = K + 1;
-    // PRE = 2: persistent blocks walk the tiles blockIdx.x + j gridDim.x, and
-    // the last component's prefetch slot loads the next tile's first one
-    constexpr bool PERS = PRE == 2;
-    const long long ntiles = (a.Q + T - 1) / T;
-    struct Tile {
-        bool valid;
-        long long samp;
-        int s;
-    };
-    auto make_tile = [&](long long tile) {
-        const long long q = tile * T + c;
-        Tile r;
-        r.valid = tile < ntiles && q < a.Q;
-        r.samp = r.valid ? q / a.MMx : 0;
-        r.s = r.valid ? (int)(q % a.MMx) : 0;
-        return r;
-    };
-    long long tile = PERS ? (long long)blockIdx.x : xcd_tile(gridDim.x);
-    Tile cur = make_tile(tile);
-    auto load = [&](const Tile& tl, int p, cpx<R>(&v)[E], int gg) {
-        const cpx<R>* __restrict__ in = static_cast<const cpx<R>*>(a.in) + tl.samp * a.in_ss + tl.s;
+    const long long q = xcd_tile(gridDim.x) * T + c;
+    const bool valid = q < a.Q;
+    const long long samp = valid ? q / a.MMx : 0;
+    const int s = valid ? (int)(q % a.MMx) : 0;
+    auto load = [&](int p, cpx<R>(&v)[E], int gg) {
+        const cpx<R>* __restrict__ in = static_cast<const cpx<R>*>(a.in) + samp * a.in_ss + s;
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int n = P::in_pos(gg, i);
-            v[i] = tl.valid ? in[p * a.in_cs + (long long)n * a.MMx] : cpx<R>{0, 0};
+            v[i] = valid ? in[p * a.in_cs + (long long)n * a.MMx] : cpx<R>{0, 0};
         }
     };
     cpx<R> nxt[PRE ? E : 1];
-    if constexpr (PRE) load(cur, 0, nxt, g);
-#pragma unroll 1
-    while (true) {
-    const long long tile_next = tile + gridDim.x;
-    const Tile nt = PERS ? make_tile(tile_next) : cur;
-    const bool valid = cur.valid;
-    const long long samp = cur.samp;
-    const int s = cur.s;
+    if constexpr (PRE) load(0, nxt, g);
     const int jy = s / Mx, kxi = s % Mx;
     const int kyi = jy <= K ? jy : jy - M;
     const R kx = (R)kxi, ky = (R)kyi;
@@ -442,10 +420,9 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
         if constexpr (PRE) {
 #pragma unroll
             for (int i = 0; i < E; ++i) v[i] = nxt[i];
-            if (p + 1 < NC) load(cur, p + 1, nxt, gg);
-            else if (PERS && tile_next < ntiles) load(nt, 0, nxt, gg);
+            if (p + 1 < NC) load(p + 1, nxt, gg);
         } else {
-            load(cur, p, v, gg);
+            load(p, v, gg);
         }
         if constexpr (SP) P::template run<-1, T, 1>(v, gg, reinterpret_cast<cpx<R>*>(reinterpret_cast<R*>(lds) + cc), twl);
         else P::template run<-1, T, 0>(v, gg, lds + cc, twl);
@@ -567,11 +544,6 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
             for (int j = 0; j < 3; ++j) o[j * a.st_cs] = b[j];
         }
     }
-    if constexpr (!PERS) break;
-    tile = tile_next;
-    if (tile >= ntiles) break;
-    cur = nt;
-    }
 }
 
 // ------------------------------------------------------------------ launch
@@ -657,13 +629,7 @@ hipError_t launch_f3(const F3Args& a, hipStream_t s)
     static_assert(tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len <= 163840, "LDS per block exceeds 160 KiB");
     static bool done = false;
     if (!cut_ok<P::N>(a.K, a.M) || a.Mx != Cut<P::N>::K + 1) return hipErrorInvalidValue;
-    long long grid = (a.Q + T - 1) / T;
-    if (PRE == 2) {
-        // persistent: as many blocks as fit at once (one per CU for 1024 threads)
-        const long long cap = (long long)device_cus() * (P::G * T >= 1024 ? 1 : 2);
-        if (grid > cap) grid = cap;
-    }
-    return launch_k(k_f3<P, T, MODE, SP, W, R, PRE>, grid, P::G * T,
+    return launch_k(k_f3<P, T, MODE, SP, W, R, PRE>, (a.Q + T - 1) / T, P::G * T,
                     tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len, s, a, done);
 }
 
