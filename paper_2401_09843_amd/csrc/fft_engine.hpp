@@ -226,8 +226,11 @@ __device__ __forceinline__ int lds_pos(int pos) { return pos + pos / PD; }
 
 // LDS slot of element pos in the exchange that follows a stage of span P
 // and radix R, for ES-byte LDS elements.  PD > 0: the padded layout above.
-// PD == 0: a per-stage padding.  The LDS serves 256 bytes (64 banks of 4
-// bytes) per cycle, i.e. a row of W = 256 / ES elements.  The stage writes
+// PD == 0: a per-stage padding.  The LDS has 32 banks of 4 bytes and serves
+// 8-byte accesses 16 lanes at a time (measured with rocprofv3's
+// SQ_LDS_BANK_CONFLICT on gfx950: a lane stride of s slots costs 4 (s - 1)
+// extra cycles per wave for s <= 16), so a conflict-free row is
+// W = LDS_ROW_BYTES / ES elements.  The stage writes
 // element (b - k) R + k + m P from lane b (k = b mod P); adding P slots
 // after every D = max(W, P R) elements spreads the lanes that share k over
 // the P-slot groups of a row, while the unit-stride reads of the next stage
@@ -236,19 +239,21 @@ __device__ __forceinline__ int lds_pos(int pos) { return pos + pos / PD; }
 // address offsets.  Stages with P >= W write at unit stride and need none.
 constexpr bool pow2c(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
+constexpr int LDS_ROW_BYTES = 128;
+
 // Period of the layout: lds_slot(x + c) = lds_slot(x) + lds_delta(c) for
 // every multiple c of it.
 template <int PD, int P, int R, int ES>
 constexpr int lds_period()
 {
-    constexpr int W = 256 / ES;
+    constexpr int W = LDS_ROW_BYTES / ES;
     return PD > 0 ? PD : (P >= W ? 1 : (P * R > W ? P * R : W));
 }
 
 template <int PD, int P, int R, int ES>
 constexpr int lds_delta(int c)
 {
-    constexpr int W = 256 / ES;
+    constexpr int W = LDS_ROW_BYTES / ES;
     return PD > 0 ? c + c / PD : (P >= W ? c : c + P * (c / lds_period<PD, P, R, ES>()));
 }
 
@@ -258,7 +263,7 @@ __device__ __forceinline__ int lds_slot(int pos)
     if constexpr (PD > 0) {
         return pos + pos / PD;
     } else {
-        constexpr int W = 256 / ES;
+        constexpr int W = LDS_ROW_BYTES / ES;
         if constexpr (P >= W) {
             return pos;
         } else {
@@ -461,7 +466,7 @@ struct Plan<N_, G_, Radices<Rs...>> {
     static constexpr int lds_len_st()
     {
         constexpr int rad[] = {Rs...};
-        constexpr int W = 256 / ES;
+        constexpr int W = LDS_ROW_BYTES / ES;
         int P = 1, ext = N_;
         for (int s = 0; s + 1 < (int)sizeof...(Rs); ++s) {
             const int R = rad[s];
