@@ -34,7 +34,8 @@ SizeKernels make32()
     add_x<PD, PD, 1, 1, R>(k, "G256 r4.4.4.4.4 U1");
     add_x<PE, PE, 2, 1, R>(k, "G128 r4.8.8.4 U2");
     add_f3<PB, 4, 1, 1, R, 1>(k, "G128 r8.8.4.4 T4 split prefetch");
-    add_f3<PB, 8, 1, 1, R>(k, "G128 r8.8.4.4 T8 split");
+    add_f3<PB, 8, 0, 1, R, 1>(k, "G128 r8.8.4.4 T8 prefetch");
+    add_f3<PE, 8, 0, 1, R, 1>(k, "G128 r4.8.8.4 T8 prefetch");
     add_f3<PB, 8, 1, 1, R, 1>(k, "G128 r8.8.4.4 T8 split prefetch");
     add_f3<PC, 8, 1, 1, R>(k, "G64 r16.16.4 T8 split");
     add_f3<PD, 4, 0, 1, R, 1>(k, "G256 r4.4.4.4.4 T4 prefetch");
