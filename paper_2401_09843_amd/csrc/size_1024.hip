@@ -23,12 +23,10 @@ SizeKernels make32()
     add_col_p<PA, 8, 0, 1, 2, R>(k, "persistent G64 r16.16.4 T8 x2");
     add_col_p<PA, 8, 1, 1, 2, R>(k, "persistent G64 r16.16.4 T8 split x2");
     add_col_p<PB, 8, 1, 1, 2, R>(k, "persistent G128 r8.8.4.4 T8 split x2");
-    add_col_p<PA, 16, 1, 1, 1, R>(k, "persistent G64 r16.16.4 T16 split x1");
     add_x<PB, PBR, 2, 3, R>(k, "G128 r8.8.4.4 U2 w3");
     add_x<PB, PBR, 2, 4, R>(k, "G128 r8.8.4.4 U2 w4");
     add_x<PE, PE, 2, 4, R>(k, "G128 r4.8.8.4 U2 w4");
     add_x<PB, PBR, 1, 1, R>(k, "G128 r8.8.4.4 U1");
-    add_x<PD, PD, 4, 1, R>(k, "G256 r4.4.4.4.4 U4");
     add_x<PB, PBR, 2, 4, R, 4>(k, "persistent G128 r8.8.4.4 U2 w4 x4");
     add_x<PD, PD, 2, 1, R>(k, "G256 r4.4.4.4.4 U2");
     add_x<PD, PD, 1, 1, R>(k, "G256 r4.4.4.4.4 U1");
