@@ -46,11 +46,11 @@ _lib = None
 
 
 def lib() -> ctypes.CDLL:
-    """Load libns.so (built by __graft_entry__.build / _build.py)."""
+    """Load libns.so (built in-tree by paper_2401_09843_amd/_build.py)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError("libns.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+            raise RuntimeError("libns.so is not built (%s); run python -m paper_2401_09843_amd._build" % LIB_PATH)
         L = ctypes.CDLL(LIB_PATH)
         P, I32, D, S = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
         PP = ctypes.POINTER(ctypes.c_void_p)

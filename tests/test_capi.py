@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def ns():
     from paper_2401_09843_amd import ns as m
     if not os.path.exists(m.LIB_PATH):
-        pytest.fail("libns.so is not built; run __graft_entry__.build()")
+        pytest.fail("libns.so is not built; run python -m paper_2401_09843_amd._build")
     m.lib()
     return m
 
