@@ -3,9 +3,12 @@
 Default workload: the seeded perturbed shear layer at N = 1024^3, FP32, s = 1.5,
 step multiplier at m_N = N/3, eps_N = 1e-3 (32/N)^2, dt from CFL 0.5; W warm-up
 steps (graph replay), then K timed steps in one ns_step call, inputs resident
-in HBM.  The timed steps run with the pass profiler on: HIP events bracket
-every pass launch on the library's stream (eager launches; --no-profile
-times graph replays instead).  Prints one JSON line with Mpts*RK-steps/s,
+in HBM.  A stage runs the plain five passes or, in the fused form, four (the
+forward z pass also writes the inverse z transform of the new state); the
+autotuner picks the faster form (--fuse / --no-fuse force one).  The
+timed steps run with the pass profiler on: HIP events bracket every pass
+launch on the library's stream (eager launches; --no-profile times graph
+replays instead).  Prints one JSON line with Mpts*RK-steps/s,
 the HBM roofline of the dominant pass (algorithmic bytes / its average
 event-timed duration in the timed region) and the CPU oracle timed on a
 bounded sample of the same workload family.
@@ -62,7 +65,8 @@ def run_ensemble(args):
         fields.append(u)
         dts.append(float(0.5 * (2 * 3.141592653589793 / n) / u.abs().sum(0).max().item()))
     print("ensemble: %d samples, %d steps" % (len(sizes), steps), file=sys.stderr, flush=True)
-    E = ns.Solver(sizes, dtype=torch.float32, graph=True, tune=not args.no_tune, tune_cache=args.tune_cache)
+    E = ns.Solver(sizes, dtype=torch.float32, graph=True, tune=not args.no_tune, tune_cache=args.tune_cache,
+                  fuse=fuse_arg(args))
     uhs = E.forward(fields)
     init = [t.clone() for t in uhs]
     E.step(uhs, dts, args.warmup)
@@ -75,7 +79,8 @@ def run_ensemble(args):
     t_batched = time.perf_counter() - t0
     # looping the plain solver (one context per grid size, one sample at a time)
     # with the schedules the ensemble runs, so that both compute the same bits
-    plain = {n: ns.Solver(n, dtype=torch.float32, graph=True, tune=False) for n in sorted(set(sizes))}
+    form = {r["N"]: r["fused"] for r in E.tune_report() if r["pass"] == "F3_fwd_z_epilogue"}
+    plain = {n: ns.Solver(n, dtype=torch.float32, graph=True, tune=False, fuse=form[n]) for n in sorted(set(sizes))}
     passes = ["I1_inv_z", "I2_inv_y", "X_c2r_prod_r2c", "F2_fwd_y", "F3_fwd_z_epilogue"]
     for r in E.tune_report():
         names = list(r["timings_ms"].keys())
@@ -121,6 +126,14 @@ def run_ensemble(args):
     print(json.dumps(out))
 
 
+def fuse_arg(args):
+    """Stage form requested on the command line: None lets the autotuner
+    choose."""
+    if args.fuse and args.no_fuse:
+        sys.exit("--fuse and --no-fuse exclude each other")
+    return True if args.fuse else (False if args.no_fuse else None)
+
+
 def kernel_source_hash() -> str:
     """SHA-256 of the HIP sources; PMC traffic figures are valid only for
     the kernels they were measured on."""
@@ -163,6 +176,9 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (JSON lines) to read or append")
     ap.add_argument("--retune", action="store_true",
                     help="at 1024^3 FP32, run the autotuner instead of starting from the committed schedule")
+    ap.add_argument("--no-fuse", action="store_true",
+                    help="run every stage as the plain five passes (no fused F3 + inverse z pass)")
+    ap.add_argument("--fuse", action="store_true", help="end every stage in the fused F3 + inverse z pass")
     ap.add_argument("--print-source-hash", action="store_true")
     ap.add_argument("--ensemble", action="store_true", help="run the 96-sample ensemble workload instead")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -215,12 +231,14 @@ def main():
         os.close(fd)
         shutil.copyfile(committed, cache)
         schedule_source = "profiles/schedule_shear1024_fp32.jsonl"
-    S = ns.Solver(n, dtype=dt_torch, graph=True, tune=not args.no_tune, tune_cache=cache)
+    S = ns.Solver(n, dtype=dt_torch, graph=True, tune=not args.no_tune, tune_cache=cache, fuse=fuse_arg(args))
     schedule = {r["pass"]: r["selected"] for r in S.tune_report()}
+    fused = [r for r in S.tune_report() if r["pass"] == "F3_fwd_z_epilogue"][0]["fused"]
     if schedule_source != "autotuner":
         with open(committed) as f:
             pinned = {d["pass"]: d["variant"] for d in map(json.loads, f)}
-        if pinned != schedule:
+        form = pinned.pop("stage_form", None)
+        if pinned != schedule or form != ("fused" if fused else "plain"):
             schedule_source = "autotuner"
         os.remove(cache)
     print("bench: schedule %s" % json.dumps(S.tune_report()), file=sys.stderr, flush=True)
@@ -253,7 +271,7 @@ def main():
     if not args.no_profile:
         prof = S.profile_read()
         S.profile(False)
-        bpl = perfmodel.pass_bytes_per_launch(n, rbytes)
+        bpl = perfmodel.pass_bytes_per_launch(n, rbytes, fused=fused)
         for name, (ms, cnt) in prof.items():
             if cnt:
                 avg = ms / cnt
@@ -263,7 +281,7 @@ def main():
         traffic = measured_traffic(dom, n, schedule.get(dom))
         roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                     "traffic": traffic, "kernel": dom, "algorithmic_bytes_per_launch": bpl[dom]}
-    step_bytes = perfmodel.step_bytes(n, rbytes)
+    step_bytes = perfmodel.step_bytes(n, rbytes, fused=fused, steps_per_call=args.steps)
     finite = bool(torch.isfinite(torch.view_as_real(uh)).all().item())
 
     cpu = None
@@ -292,6 +310,7 @@ def main():
         "passes": per_pass,
         "schedule": schedule,
         "schedule_source": schedule_source,
+        "fused_f3_inverse_z": fused,
         "finite": finite,
         "cpu_baseline": cpu,
     }

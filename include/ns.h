@@ -70,6 +70,13 @@ typedef enum { NS_F32 = 0, NS_F64 = 1 } ns_dtype;
 #define NS_USE_GRAPH    1u  /* replay each RK3 step from a captured hipGraph */
 #define NS_CHECK_FINITE 2u  /* ns_step checks the energy after the call */
 #define NS_NO_TUNE      4u  /* skip the autotuner; use the built-in schedules */
+#define NS_NO_FUSE      8u  /* stepping runs every stage as the plain five passes */
+#define NS_FUSE        16u  /* stepping ends every stage in the fused pass: the forward
+                               z pass also writes the inverse z transform of the new
+                               state, and the next stage starts at its second pass.
+                               With neither flag the autotuner times whole stages both
+                               ways and keeps the faster form per grid size (with
+                               NS_NO_TUNE: fused).  The two flags exclude each other. */
 
 /* Model and run parameters (eqs. (2.1)-(2.4)).
  *   eps    epsilon_N, the hyperviscosity amplitude; < 0 selects the default
@@ -89,7 +96,7 @@ typedef struct {
     double         m_cut;
     int32_t        q_kind;
     double         theta;
-    uint32_t       flags;      /* NS_USE_GRAPH | NS_CHECK_FINITE | NS_NO_TUNE */
+    uint32_t       flags;      /* NS_USE_GRAPH | NS_CHECK_FINITE | NS_NO_TUNE | NS_NO_FUSE | NS_FUSE */
     const char*    tune_cache; /* autotuner cache file (JSON) or NULL */
 } ns_params;
 
@@ -175,7 +182,9 @@ ns_status ns_sync(ns_ctx* ctx);
  * writes per pass p the summed device time in milliseconds ms[p] and the
  * number of launches count[p] since the last read, and resets them.
  * Passes: 0 = inverse z (I1), 1 = inverse y (I2), 2 = x (C2R, products,
- * R2C), 3 = forward y (F2), 4 = forward z + epilogue (F3). */
+ * R2C), 3 = forward y (F2), 4 = forward z + epilogue (F3).  Where the
+ * stages are fused (NS_FUSE), ns_step runs pass 0 once per call and group,
+ * and each pass 4 launch of a step also does the next stage's pass 0. */
 #define NS_NPASS 5
 ns_status ns_profile(ns_ctx* ctx, int32_t enable);
 ns_status ns_profile_read(ns_ctx* ctx, double* ms, int64_t* count);
@@ -187,9 +196,11 @@ ns_status ns_profile_read(ns_ctx* ctx, double* ms, int64_t* count);
  * Unless NS_NO_TUNE is set, ns_init times every variant on the context's
  * workspaces, keeps the fastest, and appends the choice to the tune_cache
  * file (one JSON object per line; read back when the key matches).
- * ns_set_variant overrides the choice (e.g. to test every variant);
- * ns_tune_report writes the choices and timings as JSON into buf (always
- * NUL-terminated; *needed receives the full length + 1). */
+ * ns_set_variant overrides the choice (e.g. to test every variant; a pass 4
+ * variant is used in the group's stage form); ns_tune_report writes the
+ * choices and timings as JSON into buf, with the stage form ("fused") and
+ * the stage timings on each pass-4 entry (always NUL-terminated; *needed
+ * receives the full length + 1). */
 ns_status ns_variant_count(ns_ctx* ctx, int32_t n, int32_t pass, int32_t* count);
 ns_status ns_set_variant(ns_ctx* ctx, int32_t n, int32_t pass, int32_t variant);
 ns_status ns_tune_report(ns_ctx* ctx, char* buf, size_t len, size_t* needed);

@@ -58,6 +58,11 @@ struct F3Args {
     const void* l2;
     const void* l1;
     double c2, c1;
+    // fused form of F3_RHS only: the inverse z transform of the new state,
+    // zero-padded to N rows (the next stage's first pass), written to
+    // [batch][3][N][MMx] with the input's sample / component strides; may
+    // be the input itself (each column is read in full before it is written)
+    void* zinv;
 };
 
 // Schedule variants of the tuned passes.
@@ -73,6 +78,7 @@ struct XVariant {
 struct F3Variant {
     hipError_t (*fn)(const F3Args&, hipStream_t);
     const char* name;
+    hipError_t (*fn_zi)(const F3Args&, hipStream_t);  // the same schedule, also writing zinv
 };
 
 // Launchers for one grid size and precision: variant lists of the passes of
@@ -84,7 +90,7 @@ struct SizeKernels {
     ColVariant inv[NS_MAXV];   // zero-pad compact rows M -> N, inverse
     ColVariant fwd[NS_MAXV];   // forward, keep the M retained rows
     XVariant x[NS_MAXV];       // C2R of u, six products, R2C
-    F3Variant f3[NS_MAXV];     // z forward of 6 comps + RHS / RK epilogue
+    F3Variant f3[NS_MAXV];     // z forward of 6 comps + RHS / RK epilogue (+ fused inverse z)
     hipError_t (*x_fwd3)(const XArgs&, hipStream_t);    // R2C of a real 3-component field
     hipError_t (*x_inv3)(const XArgs&, hipStream_t);    // C2R to a real 3-component field
     hipError_t (*f3_proj)(const F3Args&, hipStream_t);  // z forward of 3 comps + projection

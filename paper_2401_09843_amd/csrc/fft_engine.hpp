@@ -490,6 +490,24 @@ struct Plan<N_, G_, Radices<Rs...>> {
     // position of register element i = q * R + m at stage-0 input / final output
     __device__ __forceinline__ static constexpr int in_pos(int t, int i) { return t + (i / R0) * G + (i % R0) * (N / R0); }
     __device__ __forceinline__ static constexpr int out_pos(int t, int i) { return t + (i / RL) * G + (i % RL) * (N / RL); }
+    // Both sets are {t + k G : k < E}: in_pos has k = i / R0 + (i % R0) (E / R0)
+    // and out_pos k = i / RL + (i % RL) (E / RL).  out_slot_of_in(i) is the
+    // output slot whose position is the input position of slot i, so an
+    // output can be fed to a second transform of the same plan without
+    // leaving the thread.
+    static constexpr int out_slot_of_in(int i)
+    {
+        const int k = i / R0 + (i % R0) * (E / R0);
+        return (k % (E / RL)) * RL + k / (E / RL);
+    }
+    static constexpr bool slot_map_ok()
+    {
+        for (int i = 0; i < E; ++i) {
+            const int o = out_slot_of_in(i);
+            if (o < 0 || o >= E || i / R0 + (i % R0) * (E / R0) != o / RL + (o % RL) * (E / RL)) return false;
+        }
+        return true;
+    }
 };
 
 }  // namespace ns

@@ -371,11 +371,16 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
 
 // ------------------------------------------------------------------ F3 pass
 // PRE = 1 issues the loads of component p + 1 before the transform of p.
-template <class P, int T, int MODE, int SP, int W, typename R, int PRE = 0>
+// ZI = 1 (F3_RHS only) also transforms the new state back along z, zero-
+// padded to N rows, and writes it to a.zinv: the inverse z pass of the next
+// stage's right-hand side, done while the state is still in registers.
+template <class P, int T, int MODE, int SP, int W, typename R, int PRE = 0, int ZI = 0>
 __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
 {
     constexpr int N = P::N, E = P::E;
     constexpr int NC = MODE == F3_RHS ? 6 : 3;  // F3_PROJ and F3_ADJ take 3 components
+    static_assert(ZI == 0 || MODE == F3_RHS, "the fused inverse follows the stage epilogue");
+    static_assert(P::slot_map_ok(), "output and input slots of a thread cover the same rows");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     cpx<R>* twl = reinterpret_cast<cpx<R>*>(smem_raw + tile_bytes<P, T, SP, R>());
@@ -470,7 +475,13 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
     for (int i = 0; i < E; ++i) {
         const int n = P::out_pos(g, i);
         const int jz = compact_of(n, N, K, M);
-        if (!valid || jz < 0) continue;
+        if (!valid || jz < 0) {
+            if constexpr (ZI) {  // truncated rows enter the inverse as zeros
+#pragma unroll
+                for (int j = 0; j < 3; ++j) acc[j][i] = {0, 0};
+            }
+            continue;
+        }
         const int kzi = n <= K ? n : n - N;
         const R kz = (R)kzi;
         cpx<R> b[3];
@@ -537,11 +548,40 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
                     r.y += ca * w0.y;
                 }
                 o[j * a.st_cs] = r;
+                if constexpr (ZI) acc[j][i] = r;
             }
         } else {
             cpx<R>* o = static_cast<cpx<R>*>(a.out) + st;
 #pragma unroll
             for (int j = 0; j < 3; ++j) o[j * a.st_cs] = b[j];
+        }
+    }
+    if constexpr (ZI) {
+        // acc[j][i] holds row out_pos(g, i) of component j of the new state
+        // (zero outside the retained rows); slot i of the inverse input is
+        // row in_pos(g, i) = out_pos(g, out_slot_of_in(i)).  One rolled loop
+        // over the components keeps a single copy of the transform; it always
+        // takes acc[0] and shifts the others down (constant indices only: a
+        // component-indexed read would move acc to scratch memory).
+        cpx<R>* zo = static_cast<cpx<R>*>(a.zinv) + samp * a.in_ss + s;
+#pragma unroll 1
+        for (int j = 0; j < 3; ++j) {
+            int gg = g, cc = c;
+            asm volatile("" : "+v"(gg), "+v"(cc));
+            cpx<R> v[E];
+#pragma unroll
+            for (int i = 0; i < E; ++i) v[i] = acc[0][P::out_slot_of_in(i)];
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                acc[0][i] = acc[1][i];
+                acc[1][i] = acc[2][i];
+            }
+            if constexpr (SP) P::template run<+1, T, 1>(v, gg, reinterpret_cast<cpx<R>*>(reinterpret_cast<R*>(lds) + cc), twl);
+            else P::template run<+1, T, 0>(v, gg, lds + cc, twl);
+            if (valid) {
+#pragma unroll
+                for (int i = 0; i < E; ++i) zo[j * a.in_cs + (long long)P::out_pos(gg, i) * a.MMx] = v[i];
+            }
         }
     }
 }
@@ -622,14 +662,15 @@ hipError_t launch_x(const XArgs& a, hipStream_t s)
                     sizeof(cpx<R>) * (XL * U + TW), s, a, done);
 }
 
-template <class P, int T, int MODE, int SP, int W, typename R, int PRE = 0>
+template <class P, int T, int MODE, int SP, int W, typename R, int PRE = 0, int ZI = 0>
 hipError_t launch_f3(const F3Args& a, hipStream_t s)
 {
     static_assert(P::G * T <= 1024, "at most 1024 threads per block");
     static_assert(tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len <= 163840, "LDS per block exceeds 160 KiB");
     static bool done = false;
     if (!cut_ok<P::N>(a.K, a.M) || a.Mx != Cut<P::N>::K + 1) return hipErrorInvalidValue;
-    return launch_k(k_f3<P, T, MODE, SP, W, R, PRE>, (a.Q + T - 1) / T, P::G * T,
+    if (ZI && !a.zinv) return hipErrorInvalidValue;
+    return launch_k(k_f3<P, T, MODE, SP, W, R, PRE, ZI>, (a.Q + T - 1) / T, P::G * T,
                     tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len, s, a, done);
 }
 
@@ -670,6 +711,7 @@ struct Launch {
         add_variant(k.fwd, k.n_fwd, launch_col<P, T, -1, COL_FWD_TRUNC, SP, 1, R>, "default");
         add_variant(k.x, k.n_x, launch_x<PX, PXR, U, X_RHS, 1, R>, "default");
         add_variant(k.f3, k.n_f3, launch_f3<PF, TF, F3_RHS, SPF, 1, R>, "default");
+        k.f3[k.n_f3 - 1].fn_zi = launch_f3<PF, TF, F3_RHS, SPF, 1, R, 0, 1>;
         k.x_fwd3 = launch_x<PX, PXR, U, X_FWD3, 1, R>;
         k.x_inv3 = launch_x<PX, PXR, U, X_INV3, 1, R>;
         k.f3_proj = launch_f3<PF, TF, F3_PROJ, SPF, 1, R>;

@@ -73,7 +73,14 @@ struct Group {
     void *U2 = nullptr, *L1 = nullptr, *L2 = nullptr, *L3 = nullptr, *Sb = nullptr, *A9 = nullptr, *B9 = nullptr;
     int sel[NS_NPASS] = {0, 0, 0, 0, 0};  // chosen schedule variant per pass
     double tune_ms[NS_NPASS][NS_MAXV] = {};  // tuner timings (ms per launch), 0 = not timed
+    // stage form: SSP-RK3 stages end in the fused F3 + inverse z pass (the
+    // next stage skips I1); stage_ms: tuner timings of a plain / fused stage
+    bool fuse = true;
+    double stage_ms[2] = {0.0, 0.0};
+    double* zeros = nullptr;  // [B] zero time steps (tuner)
 };
+
+enum { FUSE_AUTO = 0, FUSE_OFF = 1, FUSE_ON = 2 };
 
 // variant count / name of pass p (I1 and I2 share the inverse column list)
 int variant_count(const SizeKernels* k, int p)
@@ -107,6 +114,7 @@ struct ns_ctx {
     std::vector<int> n;
     std::vector<int> group_of, slot_of;
     bool f64 = false;
+    int fuse_mode = 0;  // FUSE_AUTO, FUSE_OFF (NS_NO_FUSE) or FUSE_ON (NS_FUSE)
     size_t rsz = 4;  // bytes per real
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
@@ -238,6 +246,10 @@ ns_status setup_group(ns_ctx* c, Group& g)
     if ((st = dalloc(c, &g.rate, c->rsz * (3ULL * g.K * g.K + 1)))) return st;
     if ((st = dalloc(c, (void**)&g.dt, sizeof(double) * B))) return st;
     if ((st = dalloc(c, (void**)&g.ones, sizeof(double) * B))) return st;
+    if ((st = dalloc(c, (void**)&g.zeros, sizeof(double) * B))) return st;
+    g.fuse = c->fuse_mode != FUSE_OFF;  // the tuner may change it in FUSE_AUTO mode
+    for (int v = 0; v < g.kern->n_f3; ++v)
+        if (!g.kern->f3[v].fn_zi) return fail(c, NS_ERR_UNSUPPORTED, "N=%d: F3 variant %s has no fused form", N, g.kern->f3[v].name);
     if (c->f64) {
         auto tw = twiddle_table<double>(N);
         auto rt = rate_table<double>(g.K, g.eps, s, g.m_cut, c->prm.q_kind, c->prm.theta);
@@ -249,8 +261,9 @@ ns_status setup_group(ns_ctx* c, Group& g)
         if ((st = upload(c, g.tw, tw.data(), tw.size() * sizeof(float)))) return st;
         if ((st = upload(c, g.rate, rt.data(), rt.size() * sizeof(float)))) return st;
     }
-    std::vector<double> ones(B, 1.0);
+    std::vector<double> ones(B, 1.0), zeros(B, 0.0);
     if ((st = upload(c, g.ones, ones.data(), sizeof(double) * B))) return st;
+    if ((st = upload(c, g.zeros, zeros.data(), sizeof(double) * B))) return st;
     return NS_OK;
 }
 
@@ -289,7 +302,9 @@ ns_status timed(ns_ctx* c, int pass, F&& launch)
 
 // Arguments of the five passes of one right-hand-side evaluation for every
 // sample of a group: read the compact stage state us (and u0), write
-// out = ca u0 + cb us + cc dt F(us).
+// out = ca u0 + cb us + cc dt F(us).  The I1 output (I2 input) has F2's
+// sample stride 6 N MMx, so that the fused F3 + inverse z pass writes it in
+// place over the columns it has read.
 struct PassArgs {
     ColArgs i1, i2, f2;
     XArgs x;
@@ -301,10 +316,10 @@ PassArgs pass_args(const Group& g, const void* us, void* out, const void* u0, do
 {
     const long long N = g.N, B = g.B, M = g.M, Mx = g.Mx, MMx = g.MMx;
     PassArgs a;
-    // I1: [B][3][M][MMx] -> [B][3][N][MMx]
-    a.i1 = ColArgs{us, g.A, g.tw, B * 3 * MMx, MMx, 3, M * MMx, 3 * M * MMx, N * MMx, 3 * N * MMx, g.K, g.M, 1.0};
-    // I2: [B*3*N][M][Mx] -> [B*3*N][N][Mx]
-    a.i2 = ColArgs{g.A, g.Bw, g.tw, B * 3 * N * Mx, Mx, 3 * N, M * Mx, 3 * N * M * Mx, N * Mx, 3 * N * N * Mx,
+    // I1: [B][3][M][MMx] -> [B][3 of 6][N][MMx]
+    a.i1 = ColArgs{us, g.A, g.tw, B * 3 * MMx, MMx, 3, M * MMx, 3 * M * MMx, N * MMx, 6 * N * MMx, g.K, g.M, 1.0};
+    // I2: [B][3 of 6][N][M][Mx] -> [B*3*N][N][Mx]
+    a.i2 = ColArgs{g.A, g.Bw, g.tw, B * 3 * N * Mx, Mx, 3 * N, M * Mx, 6 * N * M * Mx, N * Mx, 3 * N * N * Mx,
                    g.K, g.M, 1.0};
     // X: [B][3][N*N][Mx] -> [B][6][N*N][Mx]
     a.x = XArgs{g.Bw, g.C, g.tw, B * N * N / 2, N * N * Mx, N * N * Mx, 3 * N * N * Mx, 6 * N * N * Mx, g.K, 1.0 / N};
@@ -312,12 +327,14 @@ PassArgs pass_args(const Group& g, const void* us, void* out, const void* u0, do
     a.f2 = ColArgs{g.C, g.A, g.tw, B * 6 * N * Mx, Mx, 6 * N, N * Mx, 6 * N * N * Mx, M * Mx, 6 * N * M * Mx,
                    g.K, g.M, 1.0 / N};
     // F3: [B][6][N][MMx] -> compact [B][3][M][MMx]
+    // (the fused form also writes I1 of `out` over its input: [B][3 of 6][N][MMx])
     a.f3 = F3Args{g.A, u0, us, out, g.tw, g.rate, dt, B * MMx, (int)MMx, g.Mx, g.K, g.M,
-                  6 * N * MMx, N * MMx, g.st, M * MMx, ca, cb, cc, 1.0 / N, nullptr, nullptr, 0.0, 0.0};
+                  6 * N * MMx, N * MMx, g.st, M * MMx, ca, cb, cc, 1.0 / N, nullptr, nullptr, 0.0, 0.0, g.A};
     return a;
 }
 
-hipError_t launch_pass(const Group& g, int p, int v, const PassArgs& a, hipStream_t s)
+// zi selects the fused F3 + inverse z form of pass 4
+hipError_t launch_pass(const Group& g, int p, int v, const PassArgs& a, hipStream_t s, bool zi = false)
 {
     const SizeKernels* k = g.kern;
     switch (p) {
@@ -325,7 +342,7 @@ hipError_t launch_pass(const Group& g, int p, int v, const PassArgs& a, hipStrea
         case 1: return k->inv[v].fn(a.i2, s);
         case 2: return k->x[v].fn(a.x, s);
         case 3: return k->fwd[v].fn(a.f2, s);
-        default: return k->f3[v].fn(a.f3, s);
+        default: return zi ? k->f3[v].fn_zi(a.f3, s) : k->f3[v].fn(a.f3, s);
     }
 }
 
@@ -339,16 +356,41 @@ ns_status run_rhs(ns_ctx* c, Group& g, const void* us, void* out, const void* u0
     return NS_OK;
 }
 
-// One SSP-RK3 step (eq. (2.6)) of a group in place on U0, stages in U1.
+// First pass of the right-hand side alone: the inverse z transform of us into A.
+ns_status run_i1(ns_ctx* c, Group& g, const void* us)
+{
+    const PassArgs a = pass_args(g, us, nullptr, nullptr, 0.0, 0.0, 0.0, g.dt);
+    return timed(c, 0, [&] { return launch_pass(g, 0, g.sel[0], a, c->stream); });
+}
+
+// One SSP-RK3 stage out = ca u0 + cb us + cc dt F(us).  With fusion, A holds
+// the inverse z transform of us on entry (run_i1, or the previous stage) and
+// of out on return, and the stage runs I2, X, F2 and the fused F3; without,
+// it is the plain five-pass right-hand side.
+ns_status rk3_stage(ns_ctx* c, Group& g, const void* us, void* out, const void* u0, double ca, double cb, double cc)
+{
+    if (!g.fuse) return run_rhs(c, g, us, out, u0, ca, cb, cc, g.dt);
+    const PassArgs a = pass_args(g, us, out, u0, ca, cb, cc, g.dt);
+    ns_status st;
+    for (int p = 1; p < NS_NPASS; ++p)
+        if ((st = timed(c, p, [&] { return launch_pass(g, p, g.sel[p], a, c->stream, true); }))) return st;
+    return NS_OK;
+}
+
+// Start of a run of fused stages from the state in U0.
+ns_status begin_stages(ns_ctx* c, Group& g) { return g.fuse ? run_i1(c, g, g.U0) : NS_OK; }
+
+// One SSP-RK3 step (eq. (2.6)) of a group in place on U0, stages in U1
+// (after begin_stages).
 ns_status rk3_step(ns_ctx* c, Group& g)
 {
     ns_status st;
     // u1 = u + dt F(u)
-    if ((st = run_rhs(c, g, g.U0, g.U1, nullptr, 0.0, 1.0, 1.0, g.dt))) return st;
+    if ((st = rk3_stage(c, g, g.U0, g.U1, nullptr, 0.0, 1.0, 1.0))) return st;
     // u2 = 3/4 u + 1/4 u1 + 1/4 dt F(u1)
-    if ((st = run_rhs(c, g, g.U1, g.U1, g.U0, 0.75, 0.25, 0.25, g.dt))) return st;
+    if ((st = rk3_stage(c, g, g.U1, g.U1, g.U0, 0.75, 0.25, 0.25))) return st;
     // u^{n+1} = 1/3 u + 2/3 u2 + 2/3 dt F(u2)
-    if ((st = run_rhs(c, g, g.U1, g.U0, g.U0, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0, g.dt))) return st;
+    if ((st = rk3_stage(c, g, g.U1, g.U0, g.U0, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0))) return st;
     return NS_OK;
 }
 
@@ -508,8 +550,10 @@ ns_status tape_stages(ns_ctx* c, Group& g, const void* const* tape, size_t step_
 
 // ---------------------------------------------------------------- autotuner
 // Times every schedule variant of each pass on the group's own workspaces
-// (zero-filled) and keeps the fastest; results are cached per device, size,
-// precision and batch in a file of one JSON object per line.
+// (filled with seeded random values) and keeps the fastest, then decides the
+// stage form: the plain five passes, or I2, X, F2 and the fused F3 + inverse
+// z pass, by timing whole stages both ways.  Results are cached per device,
+// size, precision and batch in a file of one JSON object per line.
 std::string tune_key(const ns_ctx* c, const Group& g)
 {
     int dev = 0;
@@ -531,15 +575,21 @@ std::string json_field(const std::string& line, const char* name)
     return b == std::string::npos ? "" : line.substr(a, b - a);
 }
 
+const char* kStageForm = "stage_form";
+
+// Reads the cached choices for key; in FUSE_AUTO mode the stage form must be
+// cached too.
 bool load_tuning(ns_ctx* c, Group& g, const std::string& path, const std::string& key)
 {
     std::ifstream f(path);
     if (!f) return false;
     int found[NS_NPASS] = {-1, -1, -1, -1, -1};
+    int form = -1;
     std::string line;
     while (std::getline(f, line)) {
         if (json_field(line, "key") != key) continue;
         const std::string pass = json_field(line, "pass"), var = json_field(line, "variant");
+        if (pass == kStageForm) form = var == "fused" ? 1 : (var == "plain" ? 0 : -1);
         for (int p = 0; p < NS_NPASS; ++p) {
             if (pass != kPassName[p]) continue;
             for (int v = 0; v < variant_count(g.kern, p); ++v)
@@ -548,12 +598,13 @@ bool load_tuning(ns_ctx* c, Group& g, const std::string& path, const std::string
     }
     for (int p = 0; p < NS_NPASS; ++p)
         if (found[p] < 0) return false;
+    if (c->fuse_mode == FUSE_AUTO && form < 0) return false;
     for (int p = 0; p < NS_NPASS; ++p) g.sel[p] = found[p];
-    (void)c;
+    if (c->fuse_mode == FUSE_AUTO) g.fuse = form == 1;
     return true;
 }
 
-void save_tuning(const Group& g, const std::string& path, const std::string& key)
+void save_tuning(const ns_ctx* c, const Group& g, const std::string& path, const std::string& key)
 {
     std::ofstream f(path, std::ios::app);
     if (!f) return;
@@ -562,6 +613,9 @@ void save_tuning(const Group& g, const std::string& path, const std::string& key
         f << "{\"key\":\"" << key << "\",\"pass\":\"" << kPassName[p] << "\",\"variant\":\""
           << variant_name(g.kern, p, v) << "\",\"ms\":" << g.tune_ms[p][v] << "}\n";
     }
+    if (c->fuse_mode == FUSE_AUTO)
+        f << "{\"key\":\"" << key << "\",\"pass\":\"" << kStageForm << "\",\"variant\":\""
+          << (g.fuse ? "fused" : "plain") << "\",\"ms\":" << g.stage_ms[g.fuse ? 1 : 0] << "}\n";
 }
 
 ns_status tune_group(ns_ctx* c, Group& g)
@@ -569,56 +623,100 @@ ns_status tune_group(ns_ctx* c, Group& g)
     const std::string key = tune_key(c, g);
     const char* path = c->tune_cache.empty() ? nullptr : c->tune_cache.c_str();
     if (path && !key.empty() && load_tuning(c, g, path, key)) return NS_OK;
+    hipStream_t s = c->stream;
     const size_t cw = cwb(c);
     // the variants are timed on seeded values in [-1, 1) rather than zeros:
     // the x pass draws more power, and runs slower, on realistic data
     const long long per = (long long)(cw / (c->f64 ? 8 : 4));  // reals per complex word
-    HIP_TRY(c, launch_fill_random(c->f64, g.U0, per * (long long)g.st * g.B, 1, c->stream));
-    HIP_TRY(c, launch_fill_random(c->f64, g.U1, per * (long long)g.st * g.B, 2, c->stream));
-    HIP_TRY(c, launch_fill_random(c->f64, g.A, per * 6LL * g.N * g.MMx * g.B, 3, c->stream));
-    HIP_TRY(c, launch_fill_random(c->f64, g.Bw, per * 3LL * g.N * g.N * g.Mx * g.B, 4, c->stream));
-    HIP_TRY(c, launch_fill_random(c->f64, g.C, per * 6LL * g.N * g.N * g.Mx * g.B, 5, c->stream));
-    const PassArgs a = pass_args(g, g.U0, g.U1, g.U0, 0.75, 0.25, 0.25, g.ones);
+    HIP_TRY(c, launch_fill_random(c->f64, g.U0, per * (long long)g.st * g.B, 1, s));
+    HIP_TRY(c, launch_fill_random(c->f64, g.U1, per * (long long)g.st * g.B, 2, s));
+    HIP_TRY(c, launch_fill_random(c->f64, g.A, per * 6LL * g.N * g.MMx * g.B, 3, s));
+    HIP_TRY(c, launch_fill_random(c->f64, g.Bw, per * 3LL * g.N * g.N * g.Mx * g.B, 4, s));
+    HIP_TRY(c, launch_fill_random(c->f64, g.C, per * 6LL * g.N * g.N * g.Mx * g.B, 5, s));
+    PassArgs a = pass_args(g, g.U0, g.U1, g.U0, 0.75, 0.25, 0.25, g.ones);
+    // single F3 launches write their fused output to C, so that repeated
+    // launches do not feed on their own results
+    a.f3.zinv = g.C;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
+    // device time per call of launch(): one warm-up call, one timed call to
+    // size the repetitions (about 20 ms in all), then the timed repetitions
+    auto time_it = [&](auto&& launch, double& out_ms) -> hipError_t {
+        hipError_t e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms1 = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms1, e0, e1);
+        const int reps = ms1 > 0 ? (int)std::min(20.0, std::max(2.0, 20.0 / ms1)) : 2;
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        out_ms = ms / reps;
+        return e;
+    };
     ns_status st = NS_OK;
+    // F3 forms to time: 0 = plain, 1 = fused
+    const bool forms[2] = {c->fuse_mode != FUSE_ON, c->fuse_mode != FUSE_OFF};
+    int best_f3[2] = {0, 0};
+    double f3_ms[2][NS_MAXV] = {};
     for (int p = 0; p < NS_NPASS && st == NS_OK; ++p) {
         const int nv = variant_count(g.kern, p);
-        int best = 0;
-        double best_ms = 1e300;
-        for (int v = 0; v < nv && nv > 1; ++v) {
-            hipError_t e = launch_pass(g, p, v, a, c->stream);  // warm-up
-            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-            if (e == hipSuccess) e = launch_pass(g, p, v, a, c->stream);
-            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms1 = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms1, e0, e1);
-            // repeat short launches for a stable estimate (about 20 ms per variant)
-            int reps = ms1 > 0 ? (int)std::min(20.0, std::max(2.0, 20.0 / ms1)) : 2;
-            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-            for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_pass(g, p, v, a, c->stream);
-            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) {
-                st = fail(c, NS_ERR_HIP, "tuning pass %s variant %s failed: %s", kPassName[p],
-                          variant_name(g.kern, p, v), hipGetErrorString(e));
-                break;
+        for (int zi = 0; zi < 2 && st == NS_OK; ++zi) {
+            if (zi == 1 && p != 4) break;
+            if (p == 4 && !forms[zi]) continue;
+            int best = 0;
+            double best_ms = 1e300;
+            for (int v = 0; v < nv && nv > 1; ++v) {
+                double ms = 0.0;
+                const hipError_t e = time_it([&] { return launch_pass(g, p, v, a, s, zi == 1); }, ms);
+                if (e != hipSuccess) {
+                    st = fail(c, NS_ERR_HIP, "tuning pass %s variant %s failed: %s", kPassName[p],
+                              variant_name(g.kern, p, v), hipGetErrorString(e));
+                    break;
+                }
+                if (p == 4) f3_ms[zi][v] = ms;
+                else g.tune_ms[p][v] = ms;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = v;
+                }
             }
-            g.tune_ms[p][v] = ms / reps;
-            if (g.tune_ms[p][v] < best_ms) {
-                best_ms = g.tune_ms[p][v];
-                best = v;
-            }
+            if (p == 4) best_f3[zi] = best;
+            else g.sel[p] = best;
         }
-        g.sel[p] = best;
     }
+    // whole stages both ways, with dt = 0 (out = us, so that repetitions
+    // keep their values) and the fused output in place as in a step
+    if (st == NS_OK && c->fuse_mode == FUSE_AUTO) {
+        const PassArgs sa = pass_args(g, g.U0, g.U1, g.U0, 0.75, 0.25, 0.25, g.zeros);
+        auto stage = [&](int zi) -> hipError_t {
+            hipError_t e = hipSuccess;
+            for (int p = zi ? 1 : 0; p < NS_NPASS && e == hipSuccess; ++p)
+                e = launch_pass(g, p, p == 4 ? best_f3[zi] : g.sel[p], sa, s, zi == 1);
+            return e;
+        };
+        g.stage_ms[0] = g.stage_ms[1] = 1e300;
+        for (int r = 0; r < 4 && st == NS_OK; ++r) {  // alternated, best of two each
+            const int zi = r & 1;
+            double ms = 0.0;
+            const hipError_t e = time_it([&] { return stage(zi); }, ms);
+            if (e != hipSuccess) st = fail(c, NS_ERR_HIP, "timing the stage forms failed: %s", hipGetErrorString(e));
+            g.stage_ms[zi] = std::min(g.stage_ms[zi], ms);
+        }
+        g.fuse = g.stage_ms[1] < g.stage_ms[0];
+    }
+    const int form = g.fuse ? 1 : 0;
+    g.sel[4] = best_f3[form];
+    for (int v = 0; v < NS_MAXV; ++v) g.tune_ms[4][v] = f3_ms[form][v];
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (st == NS_OK && path && !key.empty()) save_tuning(g, path, key);
+    if (st == NS_OK && path && !key.empty()) save_tuning(c, g, path, key);
     return st;
 }
 
@@ -707,6 +805,8 @@ ns_status ns_init(const ns_params* p, void* hip_stream, ns_ctx** out)
     if (p->q_kind != 0 && p->q_kind != 1) return fail(nullptr, NS_ERR_ARG, "q_kind must be 0 or 1");
     if (p->q_kind == 1 && !(p->theta > 0)) return fail(nullptr, NS_ERR_ARG, "theta must be > 0 for q_kind 1");
     if (!std::isfinite(p->eps) || !std::isfinite(p->m_cut)) return fail(nullptr, NS_ERR_ARG, "eps and m_cut must be finite");
+    if ((p->flags & NS_NO_FUSE) && (p->flags & NS_FUSE))
+        return fail(nullptr, NS_ERR_ARG, "NS_FUSE and NS_NO_FUSE exclude each other");
     for (int i = 0; i < p->nsamples; ++i) {
         if (!find_kernels(p->n[i], p->dtype == NS_F64))
             return fail(nullptr, NS_ERR_UNSUPPORTED, "grid size n[%d]=%d is not supported", i, p->n[i]);
@@ -717,6 +817,7 @@ ns_status ns_init(const ns_params* p, void* hip_stream, ns_ctx** out)
     c->prm.tune_cache = nullptr;
     if (p->tune_cache) c->tune_cache = p->tune_cache;
     c->f64 = p->dtype == NS_F64;
+    c->fuse_mode = (p->flags & NS_NO_FUSE) ? FUSE_OFF : ((p->flags & NS_FUSE) ? FUSE_ON : FUSE_AUTO);
     c->rsz = c->f64 ? 8 : 4;
     c->stream = (hipStream_t)hip_stream;
     c->n.assign(p->n, p->n + p->nsamples);
@@ -834,7 +935,12 @@ ns_status ns_tune_report(ns_ctx* c, char* buf, size_t len, size_t* needed)
               << variant_name(g.kern, p, g.sel[p]) << "\",\"timings_ms\":{";
             for (int v = 0; v < variant_count(g.kern, p); ++v)
                 o << (v ? "," : "") << "\"" << variant_name(g.kern, p, v) << "\":" << g.tune_ms[p][v];
-            o << "}}";
+            o << "}";
+            // the stage form, on the F3 entry (its timings are of that form)
+            if (p == 4)
+                o << ",\"fused\":" << (g.fuse ? "true" : "false") << ",\"stage_ms\":{\"plain\":" << g.stage_ms[0]
+                  << ",\"fused\":" << g.stage_ms[1] << "}";
+            o << "}";
         }
     }
     o << "]";
@@ -955,6 +1061,8 @@ ns_status ns_step(ns_ctx* c, void* const* uh, const double* dt, int32_t nsteps)
     if (nsteps == 0) return NS_OK;
     if ((st = pack_all(c, (const void* const*)uh, true))) return st;
     if ((st = set_dt(c, dt))) return st;
+    for (Group& g : c->groups)
+        if ((st = begin_stages(c, g))) return st;
     if ((c->prm.flags & NS_USE_GRAPH) && !c->profile) {
         if ((st = ensure_graph(c))) return st;
         for (int i = 0; i < nsteps; ++i) HIP_TRY(c, hipGraphLaunch(c->step_exec, c->stream));
@@ -1002,6 +1110,8 @@ ns_status ns_step_taped(ns_ctx* c, void* const* uh, const double* dt, int32_t ns
     if (nsteps == 0) return NS_OK;
     if ((st = pack_all(c, (const void* const*)uh, true))) return st;
     if ((st = set_dt(c, dt))) return st;
+    for (Group& g : c->groups)
+        if ((st = begin_stages(c, g))) return st;
     const size_t sb = 2 * c->rsz;
     for (int n = 0; n < nsteps; ++n) {
         for (Group& g : c->groups) {
@@ -1013,12 +1123,13 @@ ns_status ns_step_taped(ns_ctx* c, void* const* uh, const double* dt, int32_t ns
                 }
                 return NS_OK;
             };
+            // the stages of rk3_step, with the stage states saved in between
             if ((st = save(g.U0, 0))) return st;
-            if ((st = run_rhs(c, g, g.U0, g.U1, nullptr, 0.0, 1.0, 1.0, g.dt))) return st;
+            if ((st = rk3_stage(c, g, g.U0, g.U1, nullptr, 0.0, 1.0, 1.0))) return st;
             if ((st = save(g.U1, 1))) return st;
-            if ((st = run_rhs(c, g, g.U1, g.U1, g.U0, 0.75, 0.25, 0.25, g.dt))) return st;
+            if ((st = rk3_stage(c, g, g.U1, g.U1, g.U0, 0.75, 0.25, 0.25))) return st;
             if ((st = save(g.U1, 2))) return st;
-            if ((st = run_rhs(c, g, g.U1, g.U0, g.U0, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0, g.dt))) return st;
+            if ((st = rk3_stage(c, g, g.U1, g.U0, g.U0, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0))) return st;
         }
     }
     return unpack_all(c, uh, true);
@@ -1047,8 +1158,10 @@ ns_status ns_adjoint_step(ns_ctx* c, const void* const* uh, const void* const* t
         } else {
             for (int b = 0; b < g.B; ++b)
                 HIP_TRY(c, launch_pack(c->f64, uh[g.samples[b]], (char*)g.U0 + b * one, g.N, g.K, c->stream));
-            if ((st = run_rhs(c, g, g.U0, g.U1, nullptr, 0.0, 1.0, 1.0, g.dt))) return st;
-            if ((st = run_rhs(c, g, g.U1, g.U2, g.U0, 0.75, 0.25, 0.25, g.dt))) return st;
+            // the first two stages exactly as ns_step_taped computes them
+            if ((st = begin_stages(c, g))) return st;
+            if ((st = rk3_stage(c, g, g.U0, g.U1, nullptr, 0.0, 1.0, 1.0))) return st;
+            if ((st = rk3_stage(c, g, g.U1, g.U2, g.U0, 0.75, 0.25, 0.25))) return st;
         }
         for (int b = 0; b < g.B; ++b)
             HIP_TRY(c, launch_pack(c->f64, lam[g.samples[b]], (char*)g.L3 + b * one, g.N, g.K, c->stream));

@@ -27,7 +27,9 @@ void add_x(SizeKernels& k, const char* name)
 template <class P, int T, int SP, int W, typename R, int PRE = 0>
 void add_f3(SizeKernels& k, const char* name)
 {
+    const int before = k.n_f3;
     add_variant(k.f3, k.n_f3, launch_f3<P, T, F3_RHS, SP, W, R, PRE>, name);
+    if (k.n_f3 > before) k.f3[k.n_f3 - 1].fn_zi = launch_f3<P, T, F3_RHS, SP, W, R, PRE, 1>;
 }
 
 }  // namespace ns

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libns.so")
 
 NS_OK, NS_ERR_ARG, NS_ERR_UNSUPPORTED, NS_ERR_OOM, NS_ERR_HIP, NS_ERR_STATE, NS_ERR_NONFINITE = range(7)
 NS_F32, NS_F64 = 0, 1
-NS_USE_GRAPH, NS_CHECK_FINITE, NS_NO_TUNE = 1, 2, 4
+NS_USE_GRAPH, NS_CHECK_FINITE, NS_NO_TUNE, NS_NO_FUSE, NS_FUSE = 1, 2, 4, 8, 16
 
 # every symbol the header declares
 EXPORTS = ("ns_init", "ns_destroy", "ns_last_error", "ns_workspace_bytes", "ns_supported_sizes", "ns_forward",
@@ -107,10 +107,14 @@ class Solver:
 
     Spectra are complex tensors [3, N, N, N//2+1] (torch.fft.rfftn layout,
     norm="forward"); physical fields are real tensors [3, N, N, N].  Methods
-    taking `uhat` accept a tensor (single sample) or a list of tensors."""
+    taking `uhat` accept a tensor (single sample) or a list of tensors.
+    fuse: True ends every SSP-RK3 stage in the fused forward z + inverse z
+    pass, False runs plain five-pass stages, None lets the autotuner time
+    both per grid size (fused if tune is False)."""
 
     def __init__(self, n, dtype=torch.float32, eps=-1.0, s=1.5, m_cut=-1.0, q_kind=0, theta=1.0,
-                 graph=True, check_finite=False, tune=False, tune_cache=None, stream=None, device=None):
+                 graph=True, check_finite=False, tune=False, tune_cache=None, stream=None, device=None,
+                 fuse=None):
         self.sizes = [int(n)] if isinstance(n, int) else [int(v) for v in n]
         if dtype not in (torch.float32, torch.float64):
             raise ValueError("dtype must be torch.float32 or torch.float64")
@@ -120,7 +124,8 @@ class Solver:
         self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._L = lib()
         nn = (ctypes.c_int32 * len(self.sizes))(*self.sizes)
-        flags = (NS_USE_GRAPH if graph else 0) | (NS_CHECK_FINITE if check_finite else 0) | (0 if tune else NS_NO_TUNE)
+        flags = ((NS_USE_GRAPH if graph else 0) | (NS_CHECK_FINITE if check_finite else 0)
+                 | (0 if tune else NS_NO_TUNE) | {None: 0, True: NS_FUSE, False: NS_NO_FUSE}[fuse])
         self._cache = tune_cache.encode() if tune_cache else None
         self._prm = _Params(NS_F32 if dtype == torch.float32 else NS_F64, len(self.sizes), nn, eps, s, m_cut,
                             q_kind, theta, flags, self._cache)

@@ -15,10 +15,12 @@ def dims(n: int):
     return K, 2 * K + 1, K + 1
 
 
-def pass_cw(n: int, stage: int = 2) -> dict:
+def pass_cw(n: int, stage: int = 2, fused: bool = False) -> dict:
     """Complex words moved per pass for one right-hand side of one sample.
     stage 1 of SSP-RK3 reads one state and writes one; stages 2 and 3 read
-    two states (u^n and the stage state) and write one."""
+    two states (u^n and the stage state) and write one.  fused: F3 also
+    writes the inverse z transform of the new state (the next stage's I1
+    output), so that the next stage skips I1 and its read of the state."""
     K, M, Mx = dims(n)
     st = M * M * Mx
     state_io = 6 * st if stage == 1 else 9 * st
@@ -27,26 +29,31 @@ def pass_cw(n: int, stage: int = 2) -> dict:
         "I2_inv_y": 3 * n * M * Mx + 3 * n * n * Mx,
         "X_c2r_prod_r2c": 3 * n * n * Mx + 6 * n * n * Mx,
         "F2_fwd_y": 6 * n * n * Mx + 6 * n * M * Mx,
-        "F3_fwd_z_epilogue": 6 * n * M * Mx + state_io,
+        "F3_fwd_z_epilogue": 6 * n * M * Mx + state_io + (3 * n * M * Mx if fused else 0),
     }
 
 
-def pass_bytes_per_launch(n: int, real_bytes: int, batch: int = 1) -> dict:
+def pass_bytes_per_launch(n: int, real_bytes: int, batch: int = 1, fused: bool = False) -> dict:
     """Algorithmic bytes of one launch of each pass, averaged over the three
     RK3 stages (only F3 differs between stages)."""
     cw = 2 * real_bytes
-    s1, s2 = pass_cw(n, 1), pass_cw(n, 2)
+    s1, s2 = pass_cw(n, 1, fused), pass_cw(n, 2, fused)
     out = {}
     for p in PASSES:
         out[p] = batch * cw * (s1[p] + 2 * s2[p]) / 3.0
     return out
 
 
-def step_bytes(n: int, real_bytes: int) -> float:
-    """Algorithmic HBM bytes of one SSP-RK3 step of one sample."""
+def step_bytes(n: int, real_bytes: int, fused: bool = False, steps_per_call: int = 1) -> float:
+    """Algorithmic HBM bytes of one SSP-RK3 step of one sample.  Fused, the
+    three stages run I2, X, F2 and the fused F3, and one I1 per call of
+    steps_per_call steps starts the chain."""
     cw = 2 * real_bytes
-    s1, s2 = pass_cw(n, 1), pass_cw(n, 2)
-    return cw * (sum(s1.values()) + 2 * sum(s2.values()))
+    s1, s2 = pass_cw(n, 1, fused), pass_cw(n, 2, fused)
+    if not fused:
+        return cw * (sum(s1.values()) + 2 * sum(s2.values()))
+    per = sum(s1.values()) + 2 * sum(s2.values()) - 3 * s1["I1_inv_z"]
+    return cw * (per + s1["I1_inv_z"] / steps_per_call)
 
 
 # ---- the paper's lower bounds (Sec. 5.1, eqs. (5.1)-(5.3)), N grid, p ranks,

@@ -58,6 +58,10 @@ def test_init_rejects_bad_arguments(ns):
     assert L.ns_init(ctypes.byref(p), None, ctypes.byref(ctx)) == ns.NS_ERR_ARG
     assert L.ns_init(None, None, ctypes.byref(ctx)) == ns.NS_ERR_ARG
     assert L.ns_init(ctypes.byref(p), None, None) == ns.NS_ERR_ARG
+    p, keep = _params(ns, [32])
+    p.flags = ns.NS_FUSE | ns.NS_NO_FUSE
+    assert L.ns_init(ctypes.byref(p), None, ctypes.byref(ctx)) == ns.NS_ERR_ARG
+    assert b"exclude" in L.ns_last_error(None)
     assert ctx.value is None
     assert L.ns_destroy(None) == ns.NS_OK
 

@@ -87,6 +87,59 @@ def test_variants_full_size(ns, orc, n, dtype, tol):
         assert off <= 10 * tol ** 2 * total, (p, v)
 
 
+def _dev(a, dtype):
+    cd = torch.complex128 if dtype == torch.float64 else torch.complex64
+    return torch.from_numpy(np.ascontiguousarray(a)).to(cd).cuda()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("n", [64, 128])
+def test_fused_step_variants_small(ns, orc, n, dtype):
+    """Stepping ends each stage in the fused form of F3 (it also writes the
+    inverse z transform of the new state for the next stage, which then
+    skips I1): two SSP-RK3 steps with each F3 variant, fused and plain,
+    against the oracle."""
+    u0, _, _ = inputs.shear_layer(n, seed=5)
+    dt = inputs.cfl_dt(u0)
+    ref0 = orc.initial_state(u0)
+    ref = orc.ssprk3(ref0, n, dt, 2)
+    tol = 1e-12 if dtype == torch.float64 else 5e-6
+    for fuse in (True, False):
+        S = ns.Solver(n, dtype=dtype, graph=False, fuse=fuse)
+        for v in range(S.variant_count(n, 4)):
+            print("n=%d %s fuse=%s F3 variant %d" % (n, dtype, fuse, v), flush=True)
+            S.set_variant(n, 4, v)
+            uh = _dev(ref0, dtype)
+            S.step(uh, dt, 2)
+            assert rel(uh.cpu().numpy().astype(np.complex128), ref) <= tol, (fuse, v)
+
+
+@pytest.mark.parametrize("n,dtype", [(256, torch.float64), (512, torch.float32), (1024, torch.float32)])
+def test_fused_step_variants_full_size(ns, n, dtype):
+    """At full size, where the oracle has no whole step, each F3 variant's
+    fused step against the plain five-pass step (whose passes the variant
+    tests above pin to the oracle): two steps of the shear layer, with the
+    graph replayed, to the precision's rounding."""
+    u0, _, _ = inputs.shear_layer_torch(n, seed=0, device="cuda", dtype=dtype)
+    dt = float(0.5 * (2 * np.pi / n) / u0.abs().sum(0).max().item())
+    plain = ns.Solver(n, dtype=dtype, fuse=False)
+    uh0 = plain.forward(u0)
+    del u0
+    ref = uh0.clone()
+    plain.step(ref, dt, 2)
+    del plain
+    tol = 1e-13 if dtype == torch.float64 else 2e-6
+    S = ns.Solver(n, dtype=dtype)
+    for v in range(S.variant_count(n, 4)):
+        print("n=%d fused F3 variant %d" % (n, v), flush=True)
+        S.set_variant(n, 4, v)
+        uh = uh0.clone()
+        S.step(uh, dt, 2)
+        d = (torch.linalg.vector_norm(uh - ref) / torch.linalg.vector_norm(ref)).item()
+        assert d <= tol, (v, d)
+        del uh
+
+
 def test_tuner_picks_a_listed_variant_and_caches(ns, tmp_path):
     n = 64
     path = str(tmp_path / "tune.jsonl")
@@ -95,7 +148,16 @@ def test_tuner_picks_a_listed_variant_and_caches(ns, tmp_path):
     assert len(rep) == NPASS
     for r in rep:
         assert r["selected"] in r["timings_ms"]
+    # the stage form: whole plain and fused stages were timed, the faster kept
+    f3 = rep[-1]
+    assert f3["stage_ms"]["plain"] > 0 and f3["stage_ms"]["fused"] > 0
+    assert f3["fused"] == (f3["stage_ms"]["fused"] < f3["stage_ms"]["plain"])
     lines = open(path).read().strip().splitlines()
-    assert len(lines) == NPASS
+    assert len(lines) == NPASS + 1
     S2 = ns.Solver(n, dtype=torch.float32, tune=True, tune_cache=path)  # read back
-    assert [r["selected"] for r in S2.tune_report()] == [r["selected"] for r in rep]
+    rep2 = S2.tune_report()
+    assert [r["selected"] for r in rep2] == [r["selected"] for r in rep]
+    assert rep2[-1]["fused"] == f3["fused"]
+    # forced forms
+    for fuse in (True, False):
+        assert ns.Solver(n, dtype=torch.float32, tune=True, fuse=fuse).tune_report()[-1]["fused"] is fuse

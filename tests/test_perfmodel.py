@@ -49,3 +49,17 @@ def test_step_bytes_1024():
     b = pm.step_bytes(1024, 4)
     assert 299e9 < b < 301e9  # about 34.97 N^3 complex words
     assert b / (8 * 1024 ** 3) == pytest.approx(34.97, abs=0.01)
+
+
+def test_fused_model():
+    # N = 8: K = 2, M = 5, Mx = 3, state 3 * 75, I1 output 3 * 120 complex words.
+    # Fused, F3 also writes the next stage's I1 output; a step drops the
+    # three I1 launches (three reads of the state saved), and one I1 per
+    # call starts the chain.
+    n, cw = 8, 8
+    assert pm.pass_cw(n, 2, True)["F3_fwd_z_epilogue"] == pm.pass_cw(n, 2)["F3_fwd_z_epilogue"] + 3 * 120
+    base = pm.step_bytes(n, 4)
+    assert pm.step_bytes(n, 4, fused=True, steps_per_call=10 ** 12) == pytest.approx(base - cw * 3 * 225)
+    assert pm.step_bytes(n, 4, fused=True, steps_per_call=1) == pytest.approx(base - cw * 3 * 225 + cw * 585)
+    bpl = pm.pass_bytes_per_launch(n, 4, fused=True)
+    assert bpl["F3_fwd_z_epilogue"] == pytest.approx(pm.pass_bytes_per_launch(n, 4)["F3_fwd_z_epilogue"] + cw * 360)
