@@ -236,6 +236,101 @@ def rhs_sparse(modes: np.ndarray, coefs: np.ndarray, out_modes: np.ndarray, n: i
     return out
 
 
+def padded_cutoff(n: int) -> int:
+    """Retained wavenumbers |k_i| <= n/2 - 1 of an n-mode state: the Nyquist
+    planes k_i = -n/2 of the n-point half spectrum are left out (reading of
+    Algorithm 2, which does not treat them)."""
+    return n // 2 - 1
+
+
+def rhs_padded(uh: np.ndarray, n: int, npad: int, prm: Params = Params()) -> np.ndarray:
+    """The right-hand side by Algorithm 2 as stated, for a state of n modes
+    per axis (half spectrum [3][n][n][n/2+1]):
+      1. pad u-hat with zeros to npad >= 3n/2 points per axis,
+      2. u = F^-1[u-hat] on the padded grid,
+      3. the six products B_ij = u_i u_j,
+      4. B-hat = F[B],
+      5. drop the frequencies the n-mode state does not hold,
+      6. b = -i k.B-hat, the Leray projection (eq. (2.5)) and the
+         hyperviscosity of eqs. (2.1)-(2.4), with eps/m_cut defaults taken
+         at the mode resolution n.
+    Retained modes: |k_i| <= padded_cutoff(n); the output is zero elsewhere.
+    The transforms are numpy's FFTs (a library primitive); the spectra are
+    normalised by the number of grid points, as everywhere here."""
+    if 2 * npad < 3 * n:
+        raise ValueError("Algorithm 2 needs npad >= 3n/2 (n=%d, npad=%d)" % (n, npad))
+    K = padded_cutoff(n)
+    r = prm.resolved(n)
+    full = full_from_r2c(uh, n)  # [3][z][y][x]
+    k = np.fft.fftfreq(n, 1.0 / n).astype(np.int64)
+    src = np.flatnonzero(np.abs(k) <= K)  # n-grid indices of the retained wavenumbers
+    kr = k[src]
+    dst = kr % npad  # the same wavenumbers on the padded grid
+    # 1. pad
+    P = np.zeros((3, npad, npad, npad), dtype=np.complex128)
+    for c in range(3):
+        P[c][np.ix_(dst, dst, dst)] = full[c][np.ix_(src, src, src)]
+    # 2. inverse transform (u(x) = sum_k u-hat_k exp(i k.x))
+    u = np.real(np.fft.ifftn(P, axes=(1, 2, 3))) * float(npad) ** 3
+    del P
+    # 3.-5. products, forward transform, keep the retained frequencies
+    kz, ky, kx = np.meshgrid(kr, kr, kr, indexing="ij")
+    kv = (kx.astype(np.float64), ky.astype(np.float64), kz.astype(np.float64))
+    b = [np.zeros(kx.shape, dtype=np.complex128) for _ in range(3)]
+    for i in range(3):
+        for j in range(i, 3):
+            Bh = np.fft.fftn(u[i] * u[j]) / float(npad) ** 3
+            Bh = Bh[np.ix_(dst, dst, dst)]
+            # 6. b_i = -i sum_j k_j B_ij, with B symmetric
+            b[i] += -1j * kv[j] * Bh
+            if j != i:
+                b[j] += -1j * kv[i] * Bh
+    del u
+    k2 = kv[0] ** 2 + kv[1] ** 2 + kv[2] ** 2
+    kb = kv[0] * b[0] + kv[1] * b[1] + kv[2] * b[2]
+    safe = np.where(k2 > 0, k2, 1.0)
+    kabs = np.sqrt(k2)
+    if r.q_kind == 0:
+        q = (kabs > r.m_cut).astype(np.float64)
+    else:
+        with np.errstate(divide="ignore"):
+            q = np.where(kabs > r.m_cut, 1.0 - (r.m_cut / np.where(kabs > 0, kabs, 1.0)) ** ((2 * r.s - 1) / r.theta), 0.0)
+    rate = r.eps * k2 ** r.s * q
+    out = np.zeros_like(full)
+    for i in range(3):
+        ci = b[i] - np.where(k2 > 0, kv[i] * kb / safe, 0.0)
+        out[i][np.ix_(src, src, src)] = ci - rate * full[i][np.ix_(src, src, src)]
+    return r2c_from_full(out, n)
+
+
+def embed_padded(uh: np.ndarray, n: int, npad: int) -> np.ndarray:
+    """The retained modes of an n-mode half spectrum placed in the npad-point
+    half spectrum (zero elsewhere)."""
+    K = padded_cutoff(n)
+    full = full_from_r2c(uh, n)
+    k = np.fft.fftfreq(n, 1.0 / n).astype(np.int64)
+    src = np.flatnonzero(np.abs(k) <= K)
+    dst = k[src] % npad
+    out = np.zeros(full.shape[:-3] + (npad, npad, npad), dtype=np.complex128)
+    for c in range(full.shape[0]):
+        out[c][np.ix_(dst, dst, dst)] = full[c][np.ix_(src, src, src)]
+    return r2c_from_full(out, npad)
+
+
+def crop_padded(uh: np.ndarray, n: int, npad: int) -> np.ndarray:
+    """The inverse of embed_padded: the retained modes of an npad-point half
+    spectrum in the n-point half spectrum."""
+    K = padded_cutoff(n)
+    full = full_from_r2c(uh, npad)
+    k = np.fft.fftfreq(n, 1.0 / n).astype(np.int64)
+    src = np.flatnonzero(np.abs(k) <= K)
+    dst = k[src] % npad
+    out = np.zeros(full.shape[:-3] + (n, n, n), dtype=np.complex128)
+    for c in range(full.shape[0]):
+        out[c][np.ix_(src, src, src)] = full[c][np.ix_(dst, dst, dst)]
+    return r2c_from_full(out, n)
+
+
 def rollout_gradient(u0: np.ndarray, dt: float, nsteps: int, weight: np.ndarray, prm: Params = Params()):
     """Reference gradient of J = 1/2 sum over the full spectrum of
     weight_k |u-hat_k(T)|^2 with respect to the physical u0, through
