@@ -77,10 +77,18 @@ typedef enum { NS_F32 = 0, NS_F64 = 1 } ns_dtype;
                                With neither flag the autotuner times whole stages both
                                ways and keeps the faster form per grid size (with
                                NS_NO_TUNE: fused).  The two flags exclude each other. */
+#define NS_PAD         32u  /* Algorithm 2 in its padded form: n[i] is the number of modes
+                               per axis of the state, whose spectra use the n-point
+                               half-spectrum layout, and the passes run on the grid of
+                               3n/2 points (every product is then alias-free).  The state
+                               holds |k_i| <= n/2 - 1: the Nyquist planes k_i = -n/2 are
+                               ignored on input and written as zero.  Physical fields
+                               (ns_forward, ns_inverse) live on the 3n/2 grid; eps and
+                               m_cut defaults are taken at n. */
 
 /* Model and run parameters (eqs. (2.1)-(2.4)).
  *   eps    epsilon_N, the hyperviscosity amplitude; < 0 selects the default
- *          1e-3 * (32/N)^(2s-1) per sample.
+ *          1e-3 * (32/N)^(2s-1) per sample (N: the sample's n[i]).
  *   s      hyperviscosity order: the damping symbol is |k|^{2s} (s >= 1).
  *   m_cut  m_N: Q-hat_k = 0 for |k| <= m_N; < 0 selects N/3 per sample.
  *   q_kind 0: Q-hat_k = 1 above m_N; 1: Q-hat_k = 1 - (m_N/|k|)^((2s-1)/theta)
@@ -90,13 +98,15 @@ typedef enum { NS_F32 = 0, NS_F64 = 1 } ns_dtype;
 typedef struct {
     ns_dtype       dtype;
     int32_t        nsamples;   /* >= 1 */
-    const int32_t* n;          /* host array [nsamples]: even N, 8..1024, 2^a 3^b 5^c, and supported */
+    const int32_t* n;          /* host array [nsamples]: grid sizes N with compiled kernels
+                                  (ns_supported_sizes: 8..1536, 2^a 3^b 5^c); with NS_PAD
+                                  even mode counts n with 3n/2 supported */
     double         eps;
     double         s;
     double         m_cut;
     int32_t        q_kind;
     double         theta;
-    uint32_t       flags;      /* NS_USE_GRAPH | NS_CHECK_FINITE | NS_NO_TUNE | NS_NO_FUSE | NS_FUSE */
+    uint32_t       flags;      /* NS_USE_GRAPH | NS_CHECK_FINITE | NS_NO_TUNE | NS_NO_FUSE | NS_FUSE | NS_PAD */
     const char*    tune_cache; /* autotuner cache file (JSON) or NULL */
 } ns_params;
 

@@ -21,7 +21,8 @@
 using namespace ns;
 
 namespace ns {
-#define NS_SIZES(X) X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(60) X(64) X(80) X(96) X(120) X(128) X(256) X(512) X(1024)
+#define NS_SIZES(X) \
+    X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(60) X(64) X(80) X(96) X(120) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536)
 #define NS_DECL(n) const SizeKernels* kernels_##n(bool f64);
 NS_SIZES(NS_DECL)
 #undef NS_DECL
@@ -58,6 +59,7 @@ thread_local std::string g_init_error;
 // back-to-back so that each pass is a single launch for the whole group.
 struct Group {
     int N = 0, K = 0, M = 0, Mx = 0, B = 0;
+    int L = 0;  // grid of the caller's spectra: N, or 2N/3 for a padded n-mode state
     std::vector<int> samples;  // context sample index of batch slot b
     const SizeKernels* kern = nullptr;
     long long MMx = 0;         // M * Mx, columns of a compact plane
@@ -114,6 +116,7 @@ struct ns_ctx {
     std::vector<int> n;
     std::vector<int> group_of, slot_of;
     bool f64 = false;
+    bool pad = false;  // n[i] are mode counts; the passes run on 3n/2 points
     int fuse_mode = 0;  // FUSE_AUTO, FUSE_OFF (NS_NO_FUSE) or FUSE_ON (NS_FUSE)
     size_t rsz = 4;  // bytes per real
     hipStream_t stream = nullptr;
@@ -232,8 +235,9 @@ ns_status setup_group(ns_ctx* c, Group& g)
     g.kern = find_kernels(N, c->f64);
     if (!g.kern) return fail(c, NS_ERR_UNSUPPORTED, "grid size N=%d is not supported", N);
     const double s = c->prm.s;
-    g.eps = c->prm.eps >= 0 ? c->prm.eps : 1e-3 * std::pow(32.0 / N, 2.0 * s - 1.0);
-    g.m_cut = c->prm.m_cut >= 0 ? c->prm.m_cut : N / 3.0;
+    // defaults at the resolution of the state (the mode count when padded)
+    g.eps = c->prm.eps >= 0 ? c->prm.eps : 1e-3 * std::pow(32.0 / g.L, 2.0 * s - 1.0);
+    g.m_cut = c->prm.m_cut >= 0 ? c->prm.m_cut : g.L / 3.0;
     const size_t cw = 2 * c->rsz;
     const long long B = g.B;
     ns_status st;
@@ -407,7 +411,7 @@ ns_status pack_all(ns_ctx* c, const void* const* uh, bool to_u0)
     for (size_t i = 0; i < c->n.size(); ++i) {
         Group& g = c->groups[c->group_of[i]];
         char* dst = (char*)(to_u0 ? g.U0 : g.U1) + cwb(c) * g.st * c->slot_of[i];
-        HIP_TRY(c, launch_pack(c->f64, uh[i], dst, g.N, g.K, c->stream));
+        HIP_TRY(c, launch_pack(c->f64, uh[i], dst, g.L, g.K, c->stream));
     }
     return NS_OK;
 }
@@ -417,7 +421,7 @@ ns_status unpack_all(ns_ctx* c, void* const* uh, bool from_u0)
     for (size_t i = 0; i < c->n.size(); ++i) {
         Group& g = c->groups[c->group_of[i]];
         const char* src = (const char*)(from_u0 ? g.U0 : g.U1) + cwb(c) * g.st * c->slot_of[i];
-        HIP_TRY(c, launch_unpack(c->f64, src, uh[i], g.N, g.K, c->stream));
+        HIP_TRY(c, launch_unpack(c->f64, src, uh[i], g.L, g.K, c->stream));
     }
     return NS_OK;
 }
@@ -807,8 +811,12 @@ ns_status ns_init(const ns_params* p, void* hip_stream, ns_ctx** out)
     if (!std::isfinite(p->eps) || !std::isfinite(p->m_cut)) return fail(nullptr, NS_ERR_ARG, "eps and m_cut must be finite");
     if ((p->flags & NS_NO_FUSE) && (p->flags & NS_FUSE))
         return fail(nullptr, NS_ERR_ARG, "NS_FUSE and NS_NO_FUSE exclude each other");
+    const bool pad = (p->flags & NS_PAD) != 0;
     for (int i = 0; i < p->nsamples; ++i) {
-        if (!find_kernels(p->n[i], p->dtype == NS_F64))
+        if (pad && (p->n[i] < 8 || p->n[i] % 2 != 0 || !find_kernels(3 * p->n[i] / 2, p->dtype == NS_F64)))
+            return fail(nullptr, NS_ERR_UNSUPPORTED, "padded state of n[%d]=%d modes: grid %d is not supported", i,
+                        p->n[i], 3 * p->n[i] / 2);
+        if (!pad && !find_kernels(p->n[i], p->dtype == NS_F64))
             return fail(nullptr, NS_ERR_UNSUPPORTED, "grid size n[%d]=%d is not supported", i, p->n[i]);
     }
     ns_ctx* c = new ns_ctx;
@@ -817,6 +825,7 @@ ns_status ns_init(const ns_params* p, void* hip_stream, ns_ctx** out)
     c->prm.tune_cache = nullptr;
     if (p->tune_cache) c->tune_cache = p->tune_cache;
     c->f64 = p->dtype == NS_F64;
+    c->pad = pad;
     c->fuse_mode = (p->flags & NS_NO_FUSE) ? FUSE_OFF : ((p->flags & NS_FUSE) ? FUSE_ON : FUSE_AUTO);
     c->rsz = c->f64 ? 8 : 4;
     c->stream = (hipStream_t)hip_stream;
@@ -826,10 +835,11 @@ ns_status ns_init(const ns_params* p, void* hip_stream, ns_ctx** out)
     for (size_t i = 0; i < c->n.size(); ++i) {
         int gi = -1;
         for (size_t j = 0; j < c->groups.size(); ++j)
-            if (c->groups[j].N == c->n[i]) gi = (int)j;
+            if (c->groups[j].L == c->n[i]) gi = (int)j;
         if (gi < 0) {
             c->groups.emplace_back();
-            c->groups.back().N = c->n[i];
+            c->groups.back().L = c->n[i];
+            c->groups.back().N = pad ? 3 * c->n[i] / 2 : c->n[i];
             gi = (int)c->groups.size() - 1;
         }
         c->group_of[i] = gi;
@@ -887,10 +897,11 @@ ns_status ns_sync(ns_ctx* c)
     return NS_OK;
 }
 
+// the group of the samples of size n (the mode count when padded)
 static Group* group_of_size(ns_ctx* c, int n)
 {
     for (Group& g : c->groups)
-        if (g.N == n) return &g;
+        if (g.L == n) return &g;
     return nullptr;
 }
 
@@ -931,7 +942,7 @@ ns_status ns_tune_report(ns_ctx* c, char* buf, size_t len, size_t* needed)
         for (int p = 0; p < NS_NPASS; ++p) {
             if (!first) o << ",";
             first = false;
-            o << "{\"N\":" << g.N << ",\"batch\":" << g.B << ",\"pass\":\"" << kPassName[p] << "\",\"selected\":\""
+            o << "{\"N\":" << g.L << ",\"grid\":" << g.N << ",\"batch\":" << g.B << ",\"pass\":\"" << kPassName[p] << "\",\"selected\":\""
               << variant_name(g.kern, p, g.sel[p]) << "\",\"timings_ms\":{";
             for (int v = 0; v < variant_count(g.kern, p); ++v)
                 o << (v ? "," : "") << "\"" << variant_name(g.kern, p, v) << "\":" << g.tune_ms[p][v];
@@ -989,7 +1000,7 @@ ns_status ns_project(ns_ctx* c, void* const* uh)
     if ((st = check_ptrs(c, uh, "uhat"))) return st;
     for (size_t i = 0; i < c->n.size(); ++i) {
         Group& g = c->groups[c->group_of[i]];
-        HIP_TRY(c, launch_project(c->f64, uh[i], g.N, g.K, c->stream));
+        HIP_TRY(c, launch_project(c->f64, uh[i], g.L, g.K, c->stream));
     }
     return NS_OK;
 }
@@ -1014,7 +1025,7 @@ ns_status ns_forward(ns_ctx* c, const void* const* u, void* const* uh)
         F3Args f{g.A, nullptr, nullptr, g.U1, g.tw, g.rate, g.ones, MMx, (int)MMx, g.Mx, g.K, g.M,
                  0, N * MMx, 0, M * MMx, 0.0, 0.0, 0.0, 1.0 / N, nullptr, nullptr, 0.0, 0.0};
         HIP_TRY(c, g.kern->f3_proj(f, s));
-        HIP_TRY(c, launch_unpack(c->f64, g.U1, uh[i], g.N, g.K, s));
+        HIP_TRY(c, launch_unpack(c->f64, g.U1, uh[i], g.L, g.K, s));
     }
     return NS_OK;
 }
@@ -1028,7 +1039,7 @@ ns_status ns_inverse(ns_ctx* c, const void* const* uh, void* const* u)
         Group& g = c->groups[c->group_of[i]];
         const long long N = g.N, M = g.M, Mx = g.Mx, MMx = g.MMx;
         hipStream_t s = c->stream;
-        HIP_TRY(c, launch_pack(c->f64, uh[i], g.U1, g.N, g.K, s));
+        HIP_TRY(c, launch_pack(c->f64, uh[i], g.U1, g.L, g.K, s));
         ColArgs a1{g.U1, g.A, g.tw, 3 * MMx, MMx, 3, M * MMx, 3 * M * MMx, N * MMx, 3 * N * MMx, g.K, g.M, 1.0};
         HIP_TRY(c, g.kern->inv[g.sel[0]].fn(a1, s));
         ColArgs a2{g.A, g.Bw, g.tw, 3 * N * Mx, Mx, 3 * N, M * Mx, 3 * N * M * Mx, N * Mx, 3 * N * N * Mx,
@@ -1075,7 +1086,7 @@ ns_status ns_step(ns_ctx* c, void* const* uh, const double* dt, int32_t nsteps)
         for (size_t i = 0; i < c->n.size(); ++i) {
             Group& g = c->groups[c->group_of[i]];
             const int kb = std::min(4096, (int)std::ceil(std::sqrt(3.0) * g.K) + 2);
-            HIP_TRY(c, launch_spectrum(c->f64, uh[i], c->edev, g.N, g.K, kb, c->stream));
+            HIP_TRY(c, launch_spectrum(c->f64, uh[i], c->edev, g.L, g.K, kb, c->stream));
             std::vector<double> E(kb);
             HIP_TRY(c, hipMemcpyAsync(E.data(), c->edev, sizeof(double) * kb, hipMemcpyDeviceToHost, c->stream));
             HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1157,17 +1168,17 @@ ns_status ns_adjoint_step(ns_ctx* c, const void* const* uh, const void* const* t
             if ((st = tape_stages(c, g, tape_step, 0, 0, &un, &u1, &u2))) return st;
         } else {
             for (int b = 0; b < g.B; ++b)
-                HIP_TRY(c, launch_pack(c->f64, uh[g.samples[b]], (char*)g.U0 + b * one, g.N, g.K, c->stream));
+                HIP_TRY(c, launch_pack(c->f64, uh[g.samples[b]], (char*)g.U0 + b * one, g.L, g.K, c->stream));
             // the first two stages exactly as ns_step_taped computes them
             if ((st = begin_stages(c, g))) return st;
             if ((st = rk3_stage(c, g, g.U0, g.U1, nullptr, 0.0, 1.0, 1.0))) return st;
             if ((st = rk3_stage(c, g, g.U1, g.U2, g.U0, 0.75, 0.25, 0.25))) return st;
         }
         for (int b = 0; b < g.B; ++b)
-            HIP_TRY(c, launch_pack(c->f64, lam[g.samples[b]], (char*)g.L3 + b * one, g.N, g.K, c->stream));
+            HIP_TRY(c, launch_pack(c->f64, lam[g.samples[b]], (char*)g.L3 + b * one, g.L, g.K, c->stream));
         if ((st = adjoint_rk3(c, g, un, u1, u2))) return st;
         for (int b = 0; b < g.B; ++b)
-            HIP_TRY(c, launch_unpack(c->f64, (const char*)g.L3 + b * one, lam[g.samples[b]], g.N, g.K, c->stream));
+            HIP_TRY(c, launch_unpack(c->f64, (const char*)g.L3 + b * one, lam[g.samples[b]], g.L, g.K, c->stream));
     }
     return NS_OK;
 }
@@ -1188,14 +1199,14 @@ ns_status ns_adjoint_steps(ns_ctx* c, const void* const* tape, int32_t nsteps, c
     for (Group& g : c->groups) {
         const size_t one = g.st * sb;
         for (int b = 0; b < g.B; ++b)
-            HIP_TRY(c, launch_pack(c->f64, lam[g.samples[b]], (char*)g.L3 + b * one, g.N, g.K, c->stream));
+            HIP_TRY(c, launch_pack(c->f64, lam[g.samples[b]], (char*)g.L3 + b * one, g.L, g.K, c->stream));
         for (int step = nsteps - 1; step >= 0; --step) {
             const void *un, *u1, *u2;
             if ((st = tape_stages(c, g, tape, tape_step_bytes(c, g), step, &un, &u1, &u2))) return st;
             if ((st = adjoint_rk3(c, g, un, u1, u2))) return st;
         }
         for (int b = 0; b < g.B; ++b)
-            HIP_TRY(c, launch_unpack(c->f64, (const char*)g.L3 + b * one, lam[g.samples[b]], g.N, g.K, c->stream));
+            HIP_TRY(c, launch_unpack(c->f64, (const char*)g.L3 + b * one, lam[g.samples[b]], g.L, g.K, c->stream));
     }
     return NS_OK;
 }
@@ -1208,7 +1219,7 @@ ns_status ns_energy_spectrum(ns_ctx* c, const void* const* uh, double* E, int32_
     if (!E || kbins < 1) return fail(c, NS_ERR_ARG, "E must be non-null with kbins >= 1");
     for (size_t i = 0; i < c->n.size(); ++i) {
         Group& g = c->groups[c->group_of[i]];
-        HIP_TRY(c, launch_spectrum(c->f64, uh[i], E + i * (size_t)kbins, g.N, g.K, kbins, c->stream));
+        HIP_TRY(c, launch_spectrum(c->f64, uh[i], E + i * (size_t)kbins, g.L, g.K, kbins, c->stream));
     }
     return NS_OK;
 }

@@ -42,6 +42,12 @@ NS_SIZE_CFG(128,  8, NS_R(16, 8),         16, NS_R(8, 8, 2),       NS_R(2, 8, 8)
 NS_SIZE_CFG(256,  16, NS_R(16, 16),       32, NS_R(8, 8, 4),       NS_R(4, 8, 8),        32, NS_R(8, 8, 4),      16, 8, 8, 4, 2, 2, 0, 0, 0, 0)
 NS_SIZE_CFG(512,  64, NS_R(8, 8, 8),      64, NS_R(8, 8, 8),       NS_R(8, 8, 8),        64, NS_R(8, 8, 8),      16, 8, 8, 4, 4, 2, 0, 0, 0, 0)
 NS_SIZE_CFG(1024, 64, NS_R(16, 16, 4),    128, NS_R(8, 8, 4, 4),   NS_R(4, 4, 8, 8),     128, NS_R(8, 8, 4, 4),  16, 8, 4, 2, 2, 1, 1, 1, 0, 0)
+// the padded grids 3n/2 of n = 128, 256, 512, 1024 modes (a radix-3 stage
+// needs E = N / G divisible by 3 and by every other radix)
+NS_SIZE_CFG(192,  16, NS_R(4, 4, 4, 3),   16, NS_R(4, 4, 4, 3),    NS_R(3, 4, 4, 4),     16, NS_R(4, 4, 4, 3),   16, 8, 8, 4, 4, 2, 0, 0, 0, 0)
+NS_SIZE_CFG(384,  16, NS_R(8, 4, 4, 3),   32, NS_R(4, 4, 4, 2, 3), NS_R(3, 2, 4, 4, 4),  32, NS_R(4, 4, 4, 2, 3), 16, 8, 8, 4, 2, 2, 0, 0, 0, 0)
+NS_SIZE_CFG(768,  32, NS_R(8, 8, 4, 3),   64, NS_R(4, 4, 4, 4, 3), NS_R(3, 4, 4, 4, 4),  64, NS_R(4, 4, 4, 4, 3), 16, 8, 8, 4, 2, 1, 0, 0, 0, 0)
+NS_SIZE_CFG(1536, 64, NS_R(8, 8, 8, 3),   128, NS_R(4, 4, 4, 4, 2, 3), NS_R(3, 2, 4, 4, 4, 4), 128, NS_R(4, 4, 4, 4, 2, 3), 8, 4, 4, 2, 1, 1, 0, 0, 0, 0)
 #undef NS_SIZE_CFG
 #undef NS_R
 

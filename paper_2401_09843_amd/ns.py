@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libns.so")
 
 NS_OK, NS_ERR_ARG, NS_ERR_UNSUPPORTED, NS_ERR_OOM, NS_ERR_HIP, NS_ERR_STATE, NS_ERR_NONFINITE = range(7)
 NS_F32, NS_F64 = 0, 1
-NS_USE_GRAPH, NS_CHECK_FINITE, NS_NO_TUNE, NS_NO_FUSE, NS_FUSE = 1, 2, 4, 8, 16
+NS_USE_GRAPH, NS_CHECK_FINITE, NS_NO_TUNE, NS_NO_FUSE, NS_FUSE, NS_PAD = 1, 2, 4, 8, 16, 32
 
 # every symbol the header declares
 EXPORTS = ("ns_init", "ns_destroy", "ns_last_error", "ns_workspace_bytes", "ns_supported_sizes", "ns_forward",
@@ -110,12 +110,17 @@ class Solver:
     taking `uhat` accept a tensor (single sample) or a list of tensors.
     fuse: True ends every SSP-RK3 stage in the fused forward z + inverse z
     pass, False runs plain five-pass stages, None lets the autotuner time
-    both per grid size (fused if tune is False)."""
+    both per grid size (fused if tune is False).
+    pad: Algorithm 2 in its padded form.  n is then the number of modes per
+    axis of the state (spectra [3, n, n, n//2+1], modes |k_i| <= n/2 - 1) and
+    the passes and physical fields use the grid of 3n/2 points."""
 
     def __init__(self, n, dtype=torch.float32, eps=-1.0, s=1.5, m_cut=-1.0, q_kind=0, theta=1.0,
                  graph=True, check_finite=False, tune=False, tune_cache=None, stream=None, device=None,
-                 fuse=None):
+                 fuse=None, pad=False):
         self.sizes = [int(n)] if isinstance(n, int) else [int(v) for v in n]
+        self.pad = bool(pad)
+        self.grids = [3 * v // 2 if self.pad else v for v in self.sizes]
         if dtype not in (torch.float32, torch.float64):
             raise ValueError("dtype must be torch.float32 or torch.float64")
         self.dtype = dtype
@@ -125,7 +130,8 @@ class Solver:
         self._L = lib()
         nn = (ctypes.c_int32 * len(self.sizes))(*self.sizes)
         flags = ((NS_USE_GRAPH if graph else 0) | (NS_CHECK_FINITE if check_finite else 0)
-                 | (0 if tune else NS_NO_TUNE) | {None: 0, True: NS_FUSE, False: NS_NO_FUSE}[fuse])
+                 | (0 if tune else NS_NO_TUNE) | {None: 0, True: NS_FUSE, False: NS_NO_FUSE}[fuse]
+                 | (NS_PAD if self.pad else 0))
         self._cache = tune_cache.encode() if tune_cache else None
         self._prm = _Params(NS_F32 if dtype == torch.float32 else NS_F64, len(self.sizes), nn, eps, s, m_cut,
                             q_kind, theta, flags, self._cache)
@@ -157,7 +163,7 @@ class Solver:
         return xs
 
     def _phys(self, xs):
-        for t, n in zip(xs, self.sizes):
+        for t, n in zip(xs, self.grids):
             if t.dtype != self.dtype or t.device != self.device or not t.is_contiguous() or tuple(t.shape) != (3, n, n, n):
                 raise ValueError("field must be a contiguous %s tensor [3,%d,%d,%d] on %s"
                                  % (self.dtype, n, n, n, self.device))
@@ -178,7 +184,7 @@ class Solver:
 
     def inverse(self, uhat):
         xs = self._spec(self._list(uhat))
-        outs = [torch.empty((3, n, n, n), dtype=self.dtype, device=self.device) for n in self.sizes]
+        outs = [torch.empty((3, n, n, n), dtype=self.dtype, device=self.device) for n in self.grids]
         self._check(self._L.ns_inverse(self._ctx, _ptrs(xs), _ptrs(outs)))
         return self._ret(uhat, outs)
 
@@ -203,7 +209,7 @@ class Solver:
     def tape_step_bytes(self, n: int) -> int:
         """Bytes of one step of the tape of a sample of size n: three compact
         stage states [3][M][M][K+1] of complex numbers."""
-        K = (n - 1) // 3
+        K = (3 * n // 2 - 1) // 3 if self.pad else (n - 1) // 3
         cw = 8 if self.dtype == torch.float32 else 16
         return 9 * (2 * K + 1) ** 2 * (K + 1) * cw
 
