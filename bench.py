@@ -61,7 +61,12 @@ def run_ensemble(args):
     dev = torch.device("cuda", 0)
     fields, dts = [], []
     for i, n in enumerate(sizes):
-        u, _, _ = inputs.shear_layer_torch(n, seed=1000 + i, delta=(0.01, 0.05), device=dev, dtype=torch.float32)
+        if args.family == "shear":
+            u, _, _ = inputs.shear_layer_torch(n, seed=1000 + i, delta=(0.01, 0.05), device=dev, dtype=torch.float32)
+        elif args.family == "tg":
+            u = torch.from_numpy(inputs.perturbed_taylor_green(n, seed=1000 + i)[0]).to(dev, torch.float32)
+        else:
+            u = torch.from_numpy(inputs.cylindrical_shear(n, seed=1000 + i)[0]).to(dev, torch.float32)
         fields.append(u)
         dts.append(float(0.5 * (2 * 3.141592653589793 / n) / u.abs().sum(0).max().item()))
     print("ensemble: %d samples, %d steps" % (len(sizes), steps), file=sys.stderr, flush=True)
@@ -114,8 +119,11 @@ def run_ensemble(args):
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic: seeded shear layers, seeds 1000+i, delta ~ U[0.01,0.05]",
-        "config": {"workload": "ensemble 64x128^3 + 32x64^3 FP32", "parallelism": "single GPU"},
+        "data": {"shear": "synthetic: seeded shear layers, seeds 1000+i, delta ~ U[0.01,0.05]",
+                 "tg": "synthetic: perturbed Taylor-Green vortices (Sec. 6.1), seeds 1000+i",
+                 "cyl": "synthetic: cylindrical shear flows, sharp interface (Sec. 6.2), seeds 1000+i"}[args.family],
+        "config": {"workload": "ensemble 64x128^3 + 32x64^3 FP32", "family": args.family,
+                   "parallelism": "single GPU"},
         "looped_plain_samples_per_s": len(sizes) / (t_loop * 200.0 / steps),
         "speedup_vs_loop": t_loop / t_batched,
         "max_rel_diff_batched_vs_loop": worst,
@@ -183,6 +191,9 @@ def main():
                     help="Algorithm 2 in its padded form: --n modes per axis, passes on the 3n/2 grid")
     ap.add_argument("--print-source-hash", action="store_true")
     ap.add_argument("--ensemble", action="store_true", help="run the 96-sample ensemble workload instead")
+    ap.add_argument("--family", default="shear", choices=["shear", "tg", "cyl"],
+                    help="initial data of the ensemble: shear layers, or the paper's perturbed Taylor-Green "
+                         "vortices or cylindrical shear flows")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 2 GiB three times (PMC byte-counter calibration)")
     args = ap.parse_args()

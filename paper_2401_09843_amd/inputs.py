@@ -114,6 +114,59 @@ def shear_layer(n: int, seed: int = 0, rho: float = 0.05, delta=0.025, nmodes: i
     return u, float(delta), modes
 
 
+def unit_grid(n: int):
+    """Coordinates of the grid on the unit torus used by the paper's
+    initial-data families (x = X / 2 pi for this box's X in [0, 2 pi))."""
+    x = np.arange(n) / n
+    z, y, xx = np.meshgrid(x, x, x, indexing="ij")
+    return xx, y, z
+
+
+def perturbed_taylor_green(n: int, seed: int = 0, amp: float = 0.025):
+    """The perturbed Taylor-Green vortex of Sec. 6.1 (eqs. (6.1)-(6.3)) on
+    the unit torus: u = cos(2 pi x) sin(2 pi y) sin(2 pi z) + eps_0,
+    v = -sin(2 pi x) cos(2 pi y) sin(2 pi z) + eps_1, w = eps_2, with
+    eps_d = 1/8 sum over (i,j,k) in {0,1}^3 of delta_{d,i,j,k}
+    alpha_i(4 pi x) alpha_j(4 pi y) alpha_k(4 pi z), alpha_0 = sin,
+    alpha_1 = cos, and the 24 amplitudes delta ~ U[-amp, amp] i.i.d., drawn
+    as one array [d][i][j][k] from default_rng(seed).  Returns (u, delta)."""
+    rng = np.random.default_rng(seed)
+    delta = rng.uniform(-amp, amp, size=(3, 2, 2, 2))
+    x, y, z = unit_grid(n)
+    tp = 2.0 * np.pi
+    u = np.zeros((3, n, n, n))
+    u[0] = np.cos(tp * x) * np.sin(tp * y) * np.sin(tp * z)
+    u[1] = -np.sin(tp * x) * np.cos(tp * y) * np.sin(tp * z)
+    alpha = lambda i, t: np.sin(t) if i == 0 else np.cos(t)
+    for d in range(3):
+        for i in range(2):
+            for j in range(2):
+                for k in range(2):
+                    u[d] += delta[d, i, j, k] / 8.0 * alpha(i, 2 * tp * x) * alpha(j, 2 * tp * y) * alpha(k, 2 * tp * z)
+    return u, delta
+
+
+def cylindrical_shear(n: int, seed: int = 0, rho: float = 0.0, p: int = 10, delta: float = 0.025):
+    """The cylindrical shear flow of Sec. 6.2 (eqs. (6.4)-(6.5)) on the unit
+    torus: u = tanh(2 pi (r - 1/4) / rho) (for rho = 0: -1 where r <= 1/4,
+    else 1), v = w = 0, with r^2 = (y - 1/2 + s_y(x))^2 + (z - 1/2 + s_z(x))^2
+    and s_c(x) = delta sum_{k=1..p} a_k^c sin(2 pi k x - b_k^c), a ~ U[0,1],
+    b ~ U[0, 2 pi], drawn from default_rng(seed) in the order a^y, a^z, b^y,
+    b^z (p values each).  Returns (u, (a_y, a_z, b_y, b_z))."""
+    rng = np.random.default_rng(seed)
+    ay, az = rng.uniform(0.0, 1.0, p), rng.uniform(0.0, 1.0, p)
+    by, bz = rng.uniform(0.0, 2.0 * np.pi, p), rng.uniform(0.0, 2.0 * np.pi, p)
+    x, y, z = unit_grid(n)
+    xs = x[0, 0, :]
+    k = np.arange(1, p + 1)
+    sy = delta * np.sum(ay[:, None] * np.sin(2 * np.pi * k[:, None] * xs[None, :] - by[:, None]), axis=0)
+    sz = delta * np.sum(az[:, None] * np.sin(2 * np.pi * k[:, None] * xs[None, :] - bz[:, None]), axis=0)
+    r = np.sqrt((y - 0.5 + sy[None, None, :]) ** 2 + (z - 0.5 + sz[None, None, :]) ** 2)
+    u = np.zeros((3, n, n, n))
+    u[0] = np.where(r <= 0.25, -1.0, 1.0) if rho == 0 else np.tanh(2 * np.pi * (r - 0.25) / rho)
+    return u, (ay, az, by, bz)
+
+
 def cfl_dt(u: np.ndarray, cfl: float = 0.5) -> float:
     """dt = cfl * (2 pi / N) / max_x(|u|+|v|+|w|) of the given field."""
     n = u.shape[-1]

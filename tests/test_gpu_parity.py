@@ -207,6 +207,27 @@ def test_ensemble_matches_single_samples(ns):
         assert torch.equal(uh, uhs[i]), i
 
 
+def test_paper_families_ensemble_matches_oracle(ns, orc):
+    """The paper's initial-data families (Sec. 6) as an ensemble of uneven
+    sizes: three perturbed Taylor-Green vortices at 32^3 and two cylindrical
+    shear flows (sharp interface) at 24^3, FP64, 5 SSP-RK3 steps, each
+    sample against the oracle."""
+    fields = [inputs.perturbed_taylor_green(32, seed=s)[0] for s in range(3)]
+    fields += [inputs.cylindrical_shear(24, seed=s)[0] for s in range(2)]
+    sizes = [u.shape[-1] for u in fields]
+    dts = [inputs.cfl_dt(u) for u in fields]
+    E = ns.Solver(sizes, dtype=torch.float64)
+    uhs = E.forward([to_dev(u, torch.float64) for u in fields])
+    refs = []
+    for i, u in enumerate(fields):
+        ref0 = orc.initial_state(u)
+        assert rel(to_np(uhs[i]), ref0) <= 1e-13, i
+        refs.append(orc.ssprk3(ref0, sizes[i], dts[i], 5))
+    E.step(uhs, dts, 5)
+    for i in range(len(fields)):
+        assert rel(to_np(uhs[i]), refs[i]) <= 1e-12, i
+
+
 def test_check_finite_flags_blowup(ns):
     # dt far past the SSP-RK3 stability limit of the damped modes
     n = 32
