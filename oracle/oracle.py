@@ -214,6 +214,34 @@ def energy_spectrum(uh: np.ndarray, n: int, nbins: int) -> np.ndarray:
     return E
 
 
+def enstrophy_spectrum(uh: np.ndarray, n: int, nbins: int) -> np.ndarray:
+    """Z(kappa) = 1/2 sum over the full spectrum of |k x u-hat_k|^2 for
+    round(|k|) = kappa (the enstrophy-spectrum writer of Sec. 2.4; the
+    vorticity is i k x u-hat)."""
+    full = full_from_r2c(uh, n)
+    k1 = np.fft.fftfreq(n, 1.0 / n)
+    kz, ky, kx = np.meshgrid(k1, k1, k1, indexing="ij")
+    wx = ky * full[2] - kz * full[1]
+    wy = kz * full[0] - kx * full[2]
+    wz = kx * full[1] - ky * full[0]
+    dens = 0.5 * (np.abs(wx) ** 2 + np.abs(wy) ** 2 + np.abs(wz) ** 2)
+    shell = np.rint(np.sqrt(kx * kx + ky * ky + kz * kz)).astype(np.int64)
+    Z = np.zeros(nbins)
+    ok = shell < nbins
+    np.add.at(Z, shell[ok], dens[ok])
+    return Z
+
+
+def moments(uhs, n: int):
+    """Pointwise mean and variance of the empirical measure of Algorithm 1
+    over samples u_b = F^-1[u-hat_b] (half spectra of one size n):
+    mean = (1/B) sum_b u_b, var = (1/B) sum_b (u_b - mean)^2."""
+    us = [inverse(uh, n) for uh in uhs]
+    mean = sum(us) / len(us)
+    var = sum((u - mean) ** 2 for u in us) / len(us)
+    return mean, var
+
+
 def div_rel(uh: np.ndarray, n: int) -> float:
     full = full_from_r2c(uh, n)
     return float(lib().orc_div_rel(n, _ptr(full)))

@@ -1,0 +1,42 @@
+"""Pins of the oracle's in-situ statistics: the enstrophy spectrum (Sec.
+2.4's writers) against closed forms, and the pointwise mean and variance of
+the empirical measure (Algorithm 1, step 3) against ensembles whose moments
+are known exactly."""
+import numpy as np
+import pytest
+
+from paper_2401_09843_amd import inputs
+
+
+@pytest.mark.parametrize("k0", [1, 2, 3])
+def test_enstrophy_of_abc_flow_is_k0_squared_energy(orc, k0):
+    """curl u = k0 u for an ABC flow, so Z(kappa) = k0^2 E(kappa) shell by shell."""
+    n = 16
+    uh = orc.forward(inputs.abc_flow(n, k0=k0, A=1.0, B=0.7, C=0.4))
+    E = orc.energy_spectrum(uh, n, 12)
+    Z = orc.enstrophy_spectrum(uh, n, 12)
+    assert np.max(np.abs(Z - k0 ** 2 * E)) <= 1e-14 * Z.sum()
+    assert Z.sum() > 0
+
+
+def test_enstrophy_of_taylor_green(orc):
+    """omega = (-cos x sin y sin z, -sin x cos y sin z, 2 sin x sin y cos z):
+    mean |omega|^2 = 3/4, all in the shell round(sqrt 3) = 2."""
+    n = 16
+    Z = orc.enstrophy_spectrum(orc.forward(inputs.taylor_green(n)), n, 8)
+    assert abs(Z[2] - 3.0 / 8.0) <= 1e-15
+    assert np.sum(np.abs(np.delete(Z, 2))) <= 1e-15
+
+
+def test_moments_of_closed_form_ensembles(orc):
+    n = 8
+    u = inputs.random_field(n, seed=1)
+    c = inputs.random_field(n, seed=2)
+    # {u, -u}: mean 0, variance u^2
+    mean, var = orc.moments([orc.forward(u), orc.forward(-u)], n)
+    assert np.max(np.abs(mean)) <= 1e-15 and np.max(np.abs(var - u * u)) <= 1e-14
+    # u + b c for b = 0..B-1: mean u + c (B-1)/2, variance c^2 (B^2-1)/12
+    B = 5
+    mean, var = orc.moments([orc.forward(u + b * c) for b in range(B)], n)
+    assert np.max(np.abs(mean - (u + c * (B - 1) / 2))) <= 1e-13
+    assert np.max(np.abs(var - c * c * (B * B - 1) / 12)) <= 1e-13
