@@ -183,6 +183,21 @@ ns_status ns_adjoint_steps(ns_ctx* ctx, const void* const* tape, int32_t nsteps,
  * into the DEVICE array E_dev[nsamples][kbins].  Deterministic. */
 ns_status ns_energy_spectrum(ns_ctx* ctx, const void* const* uhat, double* E_dev, int32_t kbins);
 
+/* Enstrophy spectrum (the enstrophy-spectrum writer of Sec. 2.4):
+ * Z[i][kappa] = 1/2 sum over modes of the full spectrum with
+ * round(|k|) = kappa of |k x u-hat_k|^2 (the vorticity is i k x u-hat), same
+ * shells, layout and determinism as ns_energy_spectrum. */
+ns_status ns_enstrophy_spectrum(ns_ctx* ctx, const void* const* uhat, double* Z_dev, int32_t kbins);
+
+/* Pointwise statistics of the empirical measure of Algorithm 1 (step 3)
+ * over the samples of size n: with u_b = F^-1[T uhat_b] on the sample grid
+ * (N = n, or 3n/2 with NS_PAD), mean = (1/B) sum_b u_b and var = (1/B)
+ * sum_b (u_b - mean)^2, accumulated in FP64 in sample order (deterministic).
+ * uhat: host array [nsamples] as for every call (samples of other sizes are
+ * not read); mean_dev and var_dev: distinct device arrays of doubles
+ * [3][N][N][N], overwritten.  Uses the size group's workspaces. */
+ns_status ns_moments(ns_ctx* ctx, const void* const* uhat, int32_t n, double* mean_dev, double* var_dev);
+
 /* Synchronise the context's stream (convenience for callers without HIP). */
 ns_status ns_sync(ns_ctx* ctx);
 

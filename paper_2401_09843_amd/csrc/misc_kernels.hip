@@ -103,7 +103,9 @@ __device__ __forceinline__ long long isqrt_ll(long long v)
 // result is bitwise reproducible.
 constexpr int SPEC_THREADS = 256;
 
-template <typename R>
+// KIND 0: energy, e = |u-hat_k|^2; KIND 1: enstrophy, e = |k x u-hat_k|^2
+// (the vorticity omega-hat = i k x u-hat).
+template <typename R, int KIND>
 __global__ void __launch_bounds__(SPEC_THREADS) k_spectrum(const cpx<R>* __restrict__ u, double* E, int N, int K,
                                                            int kbins)
 {
@@ -129,9 +131,19 @@ __global__ void __launch_bounds__(SPEC_THREADS) k_spectrum(const cpx<R>* __restr
         const long long base = ((long long)nz * N + ny) * Nh;
         for (int kx = lo; kx <= hi; ++kx) {
             double e = 0.0;
-            for (int c = 0; c < 3; ++c) {
-                const cpx<R> v = u[c * plane + base + kx];
-                e += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+            if constexpr (KIND == 0) {
+                for (int c = 0; c < 3; ++c) {
+                    const cpx<R> v = u[c * plane + base + kx];
+                    e += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+                }
+            } else {
+                const cpx<R> a = u[base + kx], b = u[plane + base + kx], w = u[2 * plane + base + kx];
+                const double k0 = kx, k1 = ky, k2 = kz;
+                // (k x u)_x = ky w - kz v, (k x u)_y = kz u - kx w, (k x u)_z = kx v - ky u
+                const double cxr = k1 * w.x - k2 * b.x, cxi = k1 * w.y - k2 * b.y;
+                const double cyr = k2 * a.x - k0 * w.x, cyi = k2 * a.y - k0 * w.y;
+                const double czr = k0 * b.x - k1 * a.x, czi = k0 * b.y - k1 * a.y;
+                e = cxr * cxr + cxi * cxi + cyr * cyr + cyi * cyi + czr * czr + czi * czi;
             }
             acc += (kx == 0 ? 0.5 : 1.0) * e;
         }
@@ -180,9 +192,9 @@ __global__ void k_strain(const cpx<R>* __restrict__ lam, cpx<R>* __restrict__ S,
     }
 }
 
-__global__ void k_fill(double* p, double v, int n)
+__global__ void k_fill(double* p, double v, long long n)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
 
@@ -229,15 +241,57 @@ hipError_t launch_project(bool f64, void* u, int N, int K, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_spectrum(bool f64, const void* u, double* E, int N, int K, int kbins, hipStream_t s)
+hipError_t launch_spectrum(bool f64, const void* u, double* E, int N, int K, int kbins, hipStream_t s, int kind)
 {
     if (kbins <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill, dim3(nblocks(kbins, 256)), dim3(256), 0, s, E, 0.0, kbins);
     // shells beyond round(sqrt(3) K) are empty
     int kmax = (int)ceil(sqrt(3.0) * K) + 1;
     int nb = kbins < kmax ? kbins : kmax;
-    if (f64) hipLaunchKernelGGL(k_spectrum<double>, dim3(nb), dim3(SPEC_THREADS), 0, s, (const cpx<double>*)u, E, N, K, kbins);
-    else hipLaunchKernelGGL(k_spectrum<float>, dim3(nb), dim3(SPEC_THREADS), 0, s, (const cpx<float>*)u, E, N, K, kbins);
+    if (f64 && kind == 0) hipLaunchKernelGGL((k_spectrum<double, 0>), dim3(nb), dim3(SPEC_THREADS), 0, s, (const cpx<double>*)u, E, N, K, kbins);
+    else if (f64) hipLaunchKernelGGL((k_spectrum<double, 1>), dim3(nb), dim3(SPEC_THREADS), 0, s, (const cpx<double>*)u, E, N, K, kbins);
+    else if (kind == 0) hipLaunchKernelGGL((k_spectrum<float, 0>), dim3(nb), dim3(SPEC_THREADS), 0, s, (const cpx<float>*)u, E, N, K, kbins);
+    else hipLaunchKernelGGL((k_spectrum<float, 1>), dim3(nb), dim3(SPEC_THREADS), 0, s, (const cpx<float>*)u, E, N, K, kbins);
+    return hipGetLastError();
+}
+
+// One sample of a streaming mean / second moment (Welford): with k the
+// sample's 1-based index, d = x - mean; mean += d / k; m2 += d (x - mean).
+// Applied in sample order the result is deterministic.
+template <typename R>
+__global__ void k_welford(const R* __restrict__ x, double* mean, double* m2, long long n, int k)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v = (double)x[i];
+    const double d = v - mean[i];
+    const double mu = mean[i] + d / (double)k;
+    mean[i] = mu;
+    m2[i] += d * (v - mu);
+}
+
+__global__ void k_scale(double* p, double a, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] *= a;
+}
+
+hipError_t launch_welford(bool f64, const void* x, double* mean, double* m2, long long n, int k, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (k == 1) {  // start from zero
+        hipLaunchKernelGGL(k_fill, dim3(nblocks(n, 256)), dim3(256), 0, s, mean, 0.0, n);
+        hipLaunchKernelGGL(k_fill, dim3(nblocks(n, 256)), dim3(256), 0, s, m2, 0.0, n);
+    }
+    if (f64) hipLaunchKernelGGL(k_welford<double>, dim3(nblocks(n, 256)), dim3(256), 0, s, (const double*)x, mean, m2, n, k);
+    else hipLaunchKernelGGL(k_welford<float>, dim3(nblocks(n, 256)), dim3(256), 0, s, (const float*)x, mean, m2, n, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(double* p, double a, long long n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale, dim3(nblocks(n, 256)), dim3(256), 0, s, p, a, n);
     return hipGetLastError();
 }
 

@@ -6,7 +6,12 @@ namespace ns {
 hipError_t launch_pack(bool f64, const void* r2c, void* compact, int N, int K, hipStream_t s);
 hipError_t launch_unpack(bool f64, const void* compact, void* r2c, int N, int K, hipStream_t s);
 hipError_t launch_project(bool f64, void* r2c, int N, int K, hipStream_t s);
-hipError_t launch_spectrum(bool f64, const void* r2c, double* E, int N, int K, int kbins, hipStream_t s);
+// kind 0: energy spectrum, 1: enstrophy spectrum
+hipError_t launch_spectrum(bool f64, const void* r2c, double* E, int N, int K, int kbins, hipStream_t s, int kind = 0);
+// streaming mean / second moment over samples (k = 1-based sample index;
+// k = 1 clears mean and m2 first), and p *= a
+hipError_t launch_welford(bool f64, const void* x, double* mean, double* m2, long long n, int k, hipStream_t s);
+hipError_t launch_scale(double* p, double a, long long n, hipStream_t s);
 hipError_t launch_fill(double* p, double v, int n, hipStream_t s);
 hipError_t launch_fill_random(bool f64, void* p, long long nreal, unsigned long long seed, hipStream_t s);
 hipError_t launch_strain(bool f64, const void* lam, void* S, int K, long long batch, hipStream_t s);

@@ -1030,24 +1030,49 @@ ns_status ns_forward(ns_ctx* c, const void* const* u, void* const* uh)
     return NS_OK;
 }
 
+// Physical field u = F^-1[T uhat] of one sample of group g into u ([3][N^3]
+// reals); uses U1, A and Bw as workspaces.
+static ns_status inverse_one(ns_ctx* c, Group& g, const void* uh, void* u)
+{
+    const long long N = g.N, M = g.M, Mx = g.Mx, MMx = g.MMx;
+    hipStream_t s = c->stream;
+    HIP_TRY(c, launch_pack(c->f64, uh, g.U1, g.L, g.K, s));
+    ColArgs a1{g.U1, g.A, g.tw, 3 * MMx, MMx, 3, M * MMx, 3 * M * MMx, N * MMx, 3 * N * MMx, g.K, g.M, 1.0};
+    HIP_TRY(c, g.kern->inv[g.sel[0]].fn(a1, s));
+    ColArgs a2{g.A, g.Bw, g.tw, 3 * N * Mx, Mx, 3 * N, M * Mx, 3 * N * M * Mx, N * Mx, 3 * N * N * Mx,
+               g.K, g.M, 1.0};
+    HIP_TRY(c, g.kern->inv[g.sel[1]].fn(a2, s));
+    XArgs ax{g.Bw, u, g.tw, N * N / 2, N * N * Mx, N * N * N, 0, 0, g.K, 1.0};
+    HIP_TRY(c, g.kern->x_inv3(ax, s));
+    return NS_OK;
+}
+
 ns_status ns_inverse(ns_ctx* c, const void* const* uh, void* const* u)
 {
     CHECK_STATE(c);
     ns_status st;
     if ((st = check_ptrs(c, uh, "uhat")) || (st = check_ptrs(c, (const void* const*)u, "u_phys"))) return st;
-    for (size_t i = 0; i < c->n.size(); ++i) {
-        Group& g = c->groups[c->group_of[i]];
-        const long long N = g.N, M = g.M, Mx = g.Mx, MMx = g.MMx;
-        hipStream_t s = c->stream;
-        HIP_TRY(c, launch_pack(c->f64, uh[i], g.U1, g.L, g.K, s));
-        ColArgs a1{g.U1, g.A, g.tw, 3 * MMx, MMx, 3, M * MMx, 3 * M * MMx, N * MMx, 3 * N * MMx, g.K, g.M, 1.0};
-        HIP_TRY(c, g.kern->inv[g.sel[0]].fn(a1, s));
-        ColArgs a2{g.A, g.Bw, g.tw, 3 * N * Mx, Mx, 3 * N, M * Mx, 3 * N * M * Mx, N * Mx, 3 * N * N * Mx,
-                   g.K, g.M, 1.0};
-        HIP_TRY(c, g.kern->inv[g.sel[1]].fn(a2, s));
-        XArgs ax{g.Bw, u[i], g.tw, N * N / 2, N * N * Mx, N * N * N, 0, 0, g.K, 1.0};
-        HIP_TRY(c, g.kern->x_inv3(ax, s));
+    for (size_t i = 0; i < c->n.size(); ++i)
+        if ((st = inverse_one(c, c->groups[c->group_of[i]], uh[i], u[i]))) return st;
+    return NS_OK;
+}
+
+ns_status ns_moments(ns_ctx* c, const void* const* uh, int32_t n, double* mean, double* var)
+{
+    CHECK_STATE(c);
+    ns_status st;
+    if ((st = check_ptrs(c, uh, "uhat"))) return st;
+    if (!mean || !var || mean == var) return fail(c, NS_ERR_ARG, "mean and var must be distinct non-null device arrays");
+    Group* g = group_of_size(c, n);
+    if (!g) return fail(c, NS_ERR_ARG, "no samples of size %d", n);
+    const long long np = 3LL * g->N * g->N * g->N;
+    // each sample's physical field goes to C (4 N^3 reals or more), then one
+    // streaming update in sample order
+    for (int b = 0; b < g->B; ++b) {
+        if ((st = inverse_one(c, *g, uh[g->samples[b]], g->C))) return st;
+        HIP_TRY(c, launch_welford(c->f64, g->C, mean, var, np, b + 1, c->stream));
     }
+    HIP_TRY(c, launch_scale(var, 1.0 / g->B, np, c->stream));
     return NS_OK;
 }
 
@@ -1211,7 +1236,7 @@ ns_status ns_adjoint_steps(ns_ctx* c, const void* const* tape, int32_t nsteps, c
     return NS_OK;
 }
 
-ns_status ns_energy_spectrum(ns_ctx* c, const void* const* uh, double* E, int32_t kbins)
+static ns_status spectrum_all(ns_ctx* c, const void* const* uh, double* E, int32_t kbins, int kind)
 {
     CHECK_STATE(c);
     ns_status st;
@@ -1219,9 +1244,19 @@ ns_status ns_energy_spectrum(ns_ctx* c, const void* const* uh, double* E, int32_
     if (!E || kbins < 1) return fail(c, NS_ERR_ARG, "E must be non-null with kbins >= 1");
     for (size_t i = 0; i < c->n.size(); ++i) {
         Group& g = c->groups[c->group_of[i]];
-        HIP_TRY(c, launch_spectrum(c->f64, uh[i], E + i * (size_t)kbins, g.L, g.K, kbins, c->stream));
+        HIP_TRY(c, launch_spectrum(c->f64, uh[i], E + i * (size_t)kbins, g.L, g.K, kbins, c->stream, kind));
     }
     return NS_OK;
+}
+
+ns_status ns_energy_spectrum(ns_ctx* c, const void* const* uh, double* E, int32_t kbins)
+{
+    return spectrum_all(c, uh, E, kbins, 0);
+}
+
+ns_status ns_enstrophy_spectrum(ns_ctx* c, const void* const* uh, double* Z, int32_t kbins)
+{
+    return spectrum_all(c, uh, Z, kbins, 1);
 }
 
 }  // extern "C"

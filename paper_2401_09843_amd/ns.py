@@ -23,8 +23,8 @@ NS_USE_GRAPH, NS_CHECK_FINITE, NS_NO_TUNE, NS_NO_FUSE, NS_FUSE, NS_PAD = 1, 2, 4
 # every symbol the header declares
 EXPORTS = ("ns_init", "ns_destroy", "ns_last_error", "ns_workspace_bytes", "ns_supported_sizes", "ns_forward",
            "ns_inverse", "ns_project", "ns_rhs", "ns_step", "ns_tape_bytes", "ns_step_taped", "ns_adjoint_step", "ns_adjoint_steps",
-           "ns_energy_spectrum", "ns_sync", "ns_profile", "ns_profile_read", "ns_variant_count", "ns_set_variant",
-           "ns_tune_report")
+           "ns_energy_spectrum", "ns_enstrophy_spectrum", "ns_moments", "ns_sync", "ns_profile", "ns_profile_read",
+           "ns_variant_count", "ns_set_variant", "ns_tune_report")
 NS_NPASS = 5
 PASS_NAMES = ("I1_inv_z", "I2_inv_y", "X_c2r_prod_r2c", "F2_fwd_y", "F3_fwd_z_epilogue")
 
@@ -70,6 +70,8 @@ def lib() -> ctypes.CDLL:
             "ns_adjoint_step": [P, PP, PP, PD, PP],
             "ns_adjoint_steps": [P, PP, I32, PD, PP],
             "ns_energy_spectrum": [P, PP, P, I32],
+            "ns_enstrophy_spectrum": [P, PP, P, I32],
+            "ns_moments": [P, PP, I32, P, P],
             "ns_sync": [P],
             "ns_profile": [P, I32],
             "ns_profile_read": [P, PD, ctypes.POINTER(ctypes.c_int64)],
@@ -259,6 +261,25 @@ class Solver:
                 raise ValueError("tape too small")
         self._check(self._L.ns_adjoint_steps(self._ctx, _ptrs(tps), int(nsteps), arr, _ptrs(ls)))
         return lam
+
+    def enstrophy_spectrum(self, uhat, kbins: int):
+        xs = self._spec(self._list(uhat))
+        Z = torch.zeros((len(xs), kbins), dtype=torch.float64, device=self.device)
+        self._check(self._L.ns_enstrophy_spectrum(self._ctx, _ptrs(xs), ctypes.c_void_p(Z.data_ptr()), int(kbins)))
+        return Z
+
+    def moments(self, uhat, n: int):
+        """Pointwise mean and variance (1/B) of the physical velocity over
+        the samples of size n: two float64 tensors [3, N, N, N]."""
+        xs = self._spec(self._list(uhat))
+        if n not in self.sizes:
+            raise ValueError("no samples of size %d" % n)
+        N = self.grids[self.sizes.index(n)]
+        mean = torch.empty((3, N, N, N), dtype=torch.float64, device=self.device)
+        var = torch.empty_like(mean)
+        self._check(self._L.ns_moments(self._ctx, _ptrs(xs), int(n), ctypes.c_void_p(mean.data_ptr()),
+                                       ctypes.c_void_p(var.data_ptr())))
+        return mean, var
 
     def spectrum(self, uhat, kbins: int):
         xs = self._spec(self._list(uhat))

@@ -1,0 +1,71 @@
+"""In-situ statistics on the GPU against the oracle: the enstrophy spectrum
+(Sec. 2.4's writers) and the pointwise mean and variance over an ensemble
+(Algorithm 1, step 3), for both precisions, mixed sizes and the padded form."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2401_09843_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ns():
+    from paper_2401_09843_amd import ns as m
+    assert torch.cuda.is_available()
+    m.lib()
+    return m
+
+
+def dev(a, dtype):
+    cd = torch.complex128 if dtype == torch.float64 else torch.complex64
+    return torch.from_numpy(np.ascontiguousarray(a)).to(cd).cuda()
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-13), (torch.float32, 1e-6)])
+@pytest.mark.parametrize("n", [24, 64])
+def test_enstrophy_spectrum_matches_oracle(ns, orc, n, dtype, tol):
+    uh = orc.project(inputs.half_spectrum(inputs.random_field(n, seed=70 + n)), n)
+    S = ns.Solver(n, dtype=dtype)
+    x = dev(uh, dtype)
+    Z = S.enstrophy_spectrum(x, 80).cpu().numpy()[0]
+    ref = orc.enstrophy_spectrum(uh, n, 80)
+    assert np.max(np.abs(Z - ref)) <= tol * ref.sum()
+    assert np.array_equal(Z, S.enstrophy_spectrum(x, 80).cpu().numpy()[0])
+    # a divergence-free field: Z = sum |k|^2 |u|^2 / 2 puts shell kappa near kappa^2 E
+    E = S.spectrum(x, 80).cpu().numpy()[0]
+    k = np.arange(80)
+    ok = (E > 1e-3 * E.max()) & (k > 0)
+    assert np.all(np.abs(Z[ok] / (k[ok] ** 2 * E[ok]) - 1) <= 2.0 / np.maximum(k[ok], 1))
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_moments_match_oracle(ns, orc, dtype, tol):
+    sizes = [32, 24, 32, 32, 24, 32]
+    uhs = [orc.initial_state(inputs.perturbed_taylor_green(n, seed=40 + i)[0]) for i, n in enumerate(sizes)]
+    E = ns.Solver(sizes, dtype=dtype)
+    xs = [dev(u, dtype) for u in uhs]
+    for n in (32, 24):
+        print("moments n=%d %s" % (n, dtype), flush=True)
+        mean, var = E.moments(xs, n)
+        rm, rv = orc.moments([u for u, m in zip(uhs, sizes) if m == n], n)
+        assert np.linalg.norm(mean.cpu().numpy() - rm) <= tol * np.linalg.norm(rm)
+        assert np.linalg.norm(var.cpu().numpy() - rv) <= tol * np.linalg.norm(rv)
+        m2, v2 = E.moments(xs, n)
+        assert torch.equal(mean, m2) and torch.equal(var, v2)
+
+
+def test_moments_padded_grid(ns, orc):
+    """With NS_PAD the statistics live on the 3n/2 grid."""
+    n = 16
+    fields = [inputs.shear_layer(24, seed=s)[0] for s in range(3)]
+    E = ns.Solver([n] * 3, dtype=torch.float64, pad=True)
+    uhs = E.forward([torch.from_numpy(u).cuda() for u in fields])
+    mean, var = E.moments(uhs, n)
+    assert tuple(mean.shape) == (3, 24, 24, 24)
+    phys = E.inverse(uhs)  # per sample, on the same grid
+    rm = sum(phys) / 3
+    rv = sum((p - rm) ** 2 for p in phys) / 3
+    assert torch.max(torch.abs(mean - rm)).item() <= 1e-14
+    assert torch.max(torch.abs(var - rv)).item() <= 1e-14
