@@ -119,6 +119,14 @@ def run_ensemble(args):
     torch.cuda.synchronize()
     t_m = time.perf_counter() - t0
     zmean128 = zspec[:64].mean(0).cpu().tolist()
+    # distance between the 1-point marginals of the two halves of the 128^3 group
+    phys = torch.stack(E.inverse(uhs)[:64])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, w1_mean = E.wasserstein1(phys[:32].contiguous(), phys[32:].contiguous())
+    torch.cuda.synchronize()
+    t_w = time.perf_counter() - t0
+    del phys
     out = {
         "metric": "ensemble samples/s (96 samples: 64x128^3 + 32x64^3, 200 SSP-RK3 steps)",
         "value": len(sizes) / (t_batched * 200.0 / steps),
@@ -144,7 +152,8 @@ def run_ensemble(args):
         "mean_Z_k_128": zmean128[:44],
         "statistics": {"enstrophy_spectra_ms": t_z * 1e3, "moments_128_ms": t_m * 1e3,
                        "rms_of_mean_128": float(mom_mean.pow(2).mean().sqrt().item()),
-                       "mean_of_variance_128": float(mom_var.mean().item())},
+                       "mean_of_variance_128": float(mom_var.mean().item()),
+                       "w1_halves_128_ms": t_w * 1e3, "w1_halves_128_mean": w1_mean.cpu().tolist()},
         "schedule": E.tune_report(),
     }
     print(json.dumps(out))

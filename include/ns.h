@@ -198,6 +198,20 @@ ns_status ns_enstrophy_spectrum(ns_ctx* ctx, const void* const* uhat, double* Z_
  * [3][N][N][N], overwritten.  Uses the size group's workspaces. */
 ns_status ns_moments(ns_ctx* ctx, const void* const* uhat, int32_t n, double* mean_dev, double* var_dev);
 
+/* Distance between the 1-point marginals of two ensembles (the statistic of
+ * the paper's convergence study, Sec. 6.1): for each velocity component and
+ * grid point, the 1-D Wasserstein-1 distance W1 = integral |F_a - F_b| dt
+ * between the empirical distributions of the na values of ensemble a and the
+ * nb values of ensemble b (component by component, a reading of the paper's
+ * vector-valued marginals).  a: device array [na][3][n][n][n], b:
+ * [nb][3][n][n][n], physical fields of the context's real type (e.g. from
+ * ns_inverse); w_dev: device doubles [3][n][n][n] (the pointwise distance,
+ * overwritten); mean_dev: device doubles [3], the mean of w over the points
+ * per component, or NULL.  na, nb >= 1, na + nb <= 20480; the values are
+ * sorted per point in LDS, O((na + nb)^2) work per point.  Deterministic. */
+ns_status ns_wasserstein1(ns_ctx* ctx, const void* a, int32_t na, const void* b, int32_t nb, int32_t n,
+                          double* w_dev, double* mean_dev);
+
 /* Synchronise the context's stream (convenience for callers without HIP). */
 ns_status ns_sync(ns_ctx* ctx);
 

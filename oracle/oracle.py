@@ -242,6 +242,34 @@ def moments(uhs, n: int):
     return mean, var
 
 
+def wasserstein1_pointwise(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """1-D Wasserstein-1 distance between the empirical distributions of
+    a[:, i] (na samples) and b[:, i] (nb samples) at every position i:
+    W1 = integral over t of |F_a(t) - F_b(t)|, with F the empirical CDFs,
+    summed exactly between the merged sample values."""
+    a = np.sort(np.asarray(a, dtype=np.float64), axis=0)
+    b = np.sort(np.asarray(b, dtype=np.float64), axis=0)
+    na, nb = a.shape[0], b.shape[0]
+    t = np.sort(np.concatenate([a, b], axis=0), axis=0)  # breakpoints
+    out = np.zeros(a.shape[1:])
+    for j in range(na + nb - 1):
+        lo = t[j]
+        # F at the interval (t_j, t_{j+1}): the fraction of samples <= t_j
+        Fa = np.sum(a <= lo[None], axis=0) / na
+        Fb = np.sum(b <= lo[None], axis=0) / nb
+        out += np.abs(Fa - Fb) * (t[j + 1] - lo)
+    return out
+
+
+def wasserstein1_fields(ua: np.ndarray, ub: np.ndarray):
+    """The 1-point marginal distance between two ensembles of physical fields
+    ua [na][3][N][N][N] and ub [nb][3][N][N][N]: W1 of each component's
+    marginal at each point (reading: component by component), as a field
+    [3][N][N][N], and its mean over the points per component."""
+    w = wasserstein1_pointwise(ua.reshape(ua.shape[0], -1), ub.reshape(ub.shape[0], -1)).reshape(ua.shape[1:])
+    return w, w.reshape(3, -1).mean(axis=1)
+
+
 def div_rel(uh: np.ndarray, n: int) -> float:
     full = full_from_r2c(uh, n)
     return float(lib().orc_div_rel(n, _ptr(full)))

@@ -295,6 +295,90 @@ hipError_t launch_scale(double* p, double a, long long n, hipStream_t s)
     return hipGetLastError();
 }
 
+// 1-D Wasserstein-1 distance between the empirical distributions of
+// a[s * npts + i] (s < na) and b[s * npts + i] (s < nb) at every position i:
+// each thread sorts its two sample sets into its own LDS strip (insertion
+// sort), then walks the merged order adding |F_a - F_b| times the gap to the
+// next value (F = fraction of samples consumed so far).
+template <typename R>
+__global__ void k_w1(const R* __restrict__ a, int na, const R* __restrict__ b, int nb, long long npts,
+                     double* __restrict__ w)
+{
+    extern __shared__ double strip[];
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npts) return;
+    double* sa = strip + (long long)threadIdx.x * (na + nb);
+    double* sb = sa + na;
+    for (int s = 0; s < na; ++s) {
+        const double v = (double)a[(long long)s * npts + i];
+        int j = s;
+        while (j > 0 && sa[j - 1] > v) { sa[j] = sa[j - 1]; --j; }
+        sa[j] = v;
+    }
+    for (int s = 0; s < nb; ++s) {
+        const double v = (double)b[(long long)s * npts + i];
+        int j = s;
+        while (j > 0 && sb[j - 1] > v) { sb[j] = sb[j - 1]; --j; }
+        sb[j] = v;
+    }
+    int ia = 0, ib = 0;
+    double prev = sa[0] < sb[0] ? sa[0] : sb[0], acc = 0.0;
+    while (ia < na || ib < nb) {
+        const bool from_a = ib >= nb || (ia < na && sa[ia] <= sb[ib]);
+        const double v = from_a ? sa[ia] : sb[ib];
+        acc += fabs((double)ia / na - (double)ib / nb) * (v - prev);
+        if (from_a) ++ia;
+        else ++ib;
+        prev = v;
+    }
+    w[i] = acc;
+}
+
+// out[c] = mean of x[c * per .. (c + 1) * per) for c < ncomp: one block per
+// component, fixed-order strided sums and tree (deterministic).
+__global__ void __launch_bounds__(256) k_block_mean(const double* __restrict__ x, long long per, double* out)
+{
+    __shared__ double red[256];
+    const double* p = x + (long long)blockIdx.x * per;
+    double acc = 0.0;
+    for (long long j = threadIdx.x; j < per; j += 256) acc += p[j];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0] / (double)per;
+}
+
+hipError_t launch_w1(bool f64, const void* a, int na, const void* b, int nb, long long npts, int ncomp, double* w,
+                     double* mean, hipStream_t s)
+{
+    if (npts <= 0) return hipSuccess;
+    // threads per block so that their strips fit in 160 KiB of LDS
+    const size_t per_thread = sizeof(double) * (size_t)(na + nb);
+    int threads = 64;
+    while (threads > 1 && per_thread * threads > 163840) threads /= 2;
+    if (per_thread * threads > 163840) return hipErrorInvalidValue;
+    const size_t lds = per_thread * threads;
+    static bool attr32 = false, attr64 = false;
+    if (lds > 65536) {
+        bool& done = f64 ? attr64 : attr32;
+        if (!done) {
+            const void* fn = f64 ? reinterpret_cast<const void*>(k_w1<double>) : reinterpret_cast<const void*>(k_w1<float>);
+            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+            if (e != hipSuccess) return e;
+            done = true;
+        }
+    }
+    if (f64) hipLaunchKernelGGL(k_w1<double>, dim3(nblocks(npts, threads)), dim3(threads), lds, s, (const double*)a, na, (const double*)b, nb, npts, w);
+    else hipLaunchKernelGGL(k_w1<float>, dim3(nblocks(npts, threads)), dim3(threads), lds, s, (const float*)a, na, (const float*)b, nb, npts, w);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !mean) return e;
+    hipLaunchKernelGGL(k_block_mean, dim3(ncomp), dim3(256), 0, s, w, npts / ncomp, mean);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_random(bool f64, void* p, long long nreal, unsigned long long seed, hipStream_t s)
 {
     if (nreal <= 0) return hipSuccess;

@@ -12,6 +12,11 @@ hipError_t launch_spectrum(bool f64, const void* r2c, double* E, int N, int K, i
 // k = 1 clears mean and m2 first), and p *= a
 hipError_t launch_welford(bool f64, const void* x, double* mean, double* m2, long long n, int k, hipStream_t s);
 hipError_t launch_scale(double* p, double a, long long n, hipStream_t s);
+// pointwise 1-D Wasserstein-1 distance of two sample sets [na][npts] and
+// [nb][npts] into w [npts]; mean (if non-null) [ncomp] = mean of each of the
+// ncomp equal parts of w; fails if na + nb exceeds 20480
+hipError_t launch_w1(bool f64, const void* a, int na, const void* b, int nb, long long npts, int ncomp, double* w,
+                     double* mean, hipStream_t s);
 hipError_t launch_fill(double* p, double v, int n, hipStream_t s);
 hipError_t launch_fill_random(bool f64, void* p, long long nreal, unsigned long long seed, hipStream_t s);
 hipError_t launch_strain(bool f64, const void* lam, void* S, int K, long long batch, hipStream_t s);

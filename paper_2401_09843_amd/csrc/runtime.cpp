@@ -1236,6 +1236,17 @@ ns_status ns_adjoint_steps(ns_ctx* c, const void* const* tape, int32_t nsteps, c
     return NS_OK;
 }
 
+ns_status ns_wasserstein1(ns_ctx* c, const void* a, int32_t na, const void* b, int32_t nb, int32_t n, double* w,
+                          double* mean)
+{
+    CHECK_STATE(c);
+    if (!a || !b || !w) return fail(c, NS_ERR_ARG, "a, b and w must be non-null device arrays");
+    if (na < 1 || nb < 1 || n < 1) return fail(c, NS_ERR_ARG, "na = %d, nb = %d and n = %d must be >= 1", na, nb, n);
+    if (na + nb > 20480) return fail(c, NS_ERR_ARG, "na + nb = %d exceeds 20480", na + nb);
+    HIP_TRY(c, launch_w1(c->f64, a, na, b, nb, 3LL * n * n * n, 3, w, mean, c->stream));
+    return NS_OK;
+}
+
 static ns_status spectrum_all(ns_ctx* c, const void* const* uh, double* E, int32_t kbins, int kind)
 {
     CHECK_STATE(c);

@@ -23,7 +23,7 @@ NS_USE_GRAPH, NS_CHECK_FINITE, NS_NO_TUNE, NS_NO_FUSE, NS_FUSE, NS_PAD = 1, 2, 4
 # every symbol the header declares
 EXPORTS = ("ns_init", "ns_destroy", "ns_last_error", "ns_workspace_bytes", "ns_supported_sizes", "ns_forward",
            "ns_inverse", "ns_project", "ns_rhs", "ns_step", "ns_tape_bytes", "ns_step_taped", "ns_adjoint_step", "ns_adjoint_steps",
-           "ns_energy_spectrum", "ns_enstrophy_spectrum", "ns_moments", "ns_sync", "ns_profile", "ns_profile_read",
+           "ns_energy_spectrum", "ns_enstrophy_spectrum", "ns_moments", "ns_wasserstein1", "ns_sync", "ns_profile", "ns_profile_read",
            "ns_variant_count", "ns_set_variant", "ns_tune_report")
 NS_NPASS = 5
 PASS_NAMES = ("I1_inv_z", "I2_inv_y", "X_c2r_prod_r2c", "F2_fwd_y", "F3_fwd_z_epilogue")
@@ -72,6 +72,7 @@ def lib() -> ctypes.CDLL:
             "ns_energy_spectrum": [P, PP, P, I32],
             "ns_enstrophy_spectrum": [P, PP, P, I32],
             "ns_moments": [P, PP, I32, P, P],
+            "ns_wasserstein1": [P, P, I32, P, I32, I32, P, P],
             "ns_sync": [P],
             "ns_profile": [P, I32],
             "ns_profile_read": [P, PD, ctypes.POINTER(ctypes.c_int64)],
@@ -280,6 +281,26 @@ class Solver:
         self._check(self._L.ns_moments(self._ctx, _ptrs(xs), int(n), ctypes.c_void_p(mean.data_ptr()),
                                        ctypes.c_void_p(var.data_ptr())))
         return mean, var
+
+    def wasserstein1(self, a: torch.Tensor, b: torch.Tensor):
+        """Pointwise W1 between the 1-point marginals (component by
+        component) of two ensembles of physical fields a [na, 3, n, n, n] and
+        b [nb, 3, n, n, n]: returns (w [3, n, n, n], mean over points [3]),
+        float64."""
+        for t in (a, b):
+            if t.dim() != 5 or t.shape[1] != 3 or t.dtype != self.dtype or t.device != self.device \
+                    or not t.is_contiguous() or not (t.shape[2] == t.shape[3] == t.shape[4]):
+                raise ValueError("ensembles must be contiguous %s tensors [m, 3, n, n, n] on %s"
+                                 % (self.dtype, self.device))
+        if a.shape[2:] != b.shape[2:]:
+            raise ValueError("the two ensembles must share the grid")
+        n = a.shape[-1]
+        w = torch.empty(a.shape[1:], dtype=torch.float64, device=self.device)
+        mean = torch.empty(3, dtype=torch.float64, device=self.device)
+        self._check(self._L.ns_wasserstein1(self._ctx, ctypes.c_void_p(a.data_ptr()), int(a.shape[0]),
+                                            ctypes.c_void_p(b.data_ptr()), int(b.shape[0]), int(n),
+                                            ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(mean.data_ptr())))
+        return w, mean
 
     def spectrum(self, uhat, kbins: int):
         xs = self._spec(self._list(uhat))

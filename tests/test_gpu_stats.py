@@ -69,3 +69,46 @@ def test_moments_padded_grid(ns, orc):
     rv = sum((p - rm) ** 2 for p in phys) / 3
     assert torch.max(torch.abs(mean - rm)).item() <= 1e-14
     assert torch.max(torch.abs(var - rv)).item() <= 1e-14
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("n,na,nb", [(8, 5, 9), (16, 32, 32), (8, 1, 3)])
+def test_wasserstein1_matches_oracle(ns, orc, n, na, nb, dtype):
+    g = torch.Generator(device="cpu").manual_seed(100 * n + na)
+    a = torch.randn((na, 3, n, n, n), generator=g, dtype=torch.float64).to(dtype)
+    b = (0.3 + 1.5 * torch.randn((nb, 3, n, n, n), generator=g, dtype=torch.float64)).to(dtype)
+    S = ns.Solver(16, dtype=dtype)
+    w, mean = S.wasserstein1(a.cuda(), b.cuda())
+    rw, rmean = orc.wasserstein1_fields(a.double().numpy(), b.double().numpy())
+    assert np.max(np.abs(w.cpu().numpy() - rw)) <= 1e-13 * np.max(rw)
+    assert np.max(np.abs(mean.cpu().numpy() - rmean)) <= 1e-13 * np.max(rmean)
+    w2, _ = S.wasserstein1(a.cuda(), b.cuda())
+    assert torch.equal(w, w2)
+
+
+def test_wasserstein1_between_ensembles_of_the_paper_family(ns, orc):
+    """Two ensembles of perturbed Taylor-Green vortices (8 seeds each) after a
+    few steps: the distance between their 1-point marginals against the
+    oracle on the same physical fields, and zero against themselves."""
+    n, B, steps = 24, 8, 3
+    fields = [inputs.perturbed_taylor_green(n, seed=s)[0] for s in range(2 * B)]
+    E = ns.Solver([n] * (2 * B), dtype=torch.float64)
+    uhs = E.forward([torch.from_numpy(u).cuda() for u in fields])
+    E.step(uhs, [inputs.cfl_dt(u) for u in fields], steps)
+    phys = torch.stack(E.inverse(uhs))
+    a, b = phys[:B].contiguous(), phys[B:].contiguous()
+    w, mean = E.wasserstein1(a, b)
+    rw, rmean = orc.wasserstein1_fields(a.cpu().numpy(), b.cpu().numpy())
+    assert np.max(np.abs(w.cpu().numpy() - rw)) <= 1e-13 * np.max(rw)
+    assert np.all(mean.cpu().numpy() > 0)
+    w0, m0 = E.wasserstein1(a, a)
+    assert torch.all(w0 == 0) and torch.all(m0 == 0)
+
+
+def test_wasserstein1_rejects_bad_arguments(ns):
+    S = ns.Solver(16, dtype=torch.float32)
+    a = torch.zeros((2, 3, 8, 8, 8), dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        S.wasserstein1(a, torch.zeros((2, 3, 4, 4, 4), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        S.wasserstein1(a, a.double())

@@ -40,3 +40,28 @@ def test_moments_of_closed_form_ensembles(orc):
     mean, var = orc.moments([orc.forward(u + b * c) for b in range(B)], n)
     assert np.max(np.abs(mean - (u + c * (B - 1) / 2))) <= 1e-13
     assert np.max(np.abs(var - c * c * (B * B - 1) / 12)) <= 1e-13
+
+
+def test_wasserstein_closed_forms(orc):
+    rng = np.random.default_rng(0)
+    a = rng.standard_normal((7, 50))
+    assert np.max(np.abs(orc.wasserstein1_pointwise(a, a))) == 0.0
+    # a shift by c moves every quantile by c
+    assert np.max(np.abs(orc.wasserstein1_pointwise(a, a + 0.3) - 0.3)) <= 1e-14
+    # equal counts: the mean distance between order statistics
+    b = rng.standard_normal((7, 50))
+    ref = np.mean(np.abs(np.sort(a, axis=0) - np.sort(b, axis=0)), axis=0)
+    assert np.max(np.abs(orc.wasserstein1_pointwise(a, b) - ref)) <= 1e-14
+    # unequal counts: point masses {0} and {0, 1}: half the mass moves by 1
+    assert abs(orc.wasserstein1_pointwise(np.zeros((1, 1)), np.array([[0.0], [1.0]]))[0] - 0.5) <= 1e-15
+
+
+def test_wasserstein_matches_scipy(orc):
+    """The textbook routine for unequal ensembles (scipy.stats)."""
+    from scipy.stats import wasserstein_distance
+    rng = np.random.default_rng(1)
+    a = rng.standard_normal((5, 40))
+    b = 0.5 + 2.0 * rng.standard_normal((9, 40))
+    got = orc.wasserstein1_pointwise(a, b)
+    ref = np.array([wasserstein_distance(a[:, i], b[:, i]) for i in range(40)])
+    assert np.max(np.abs(got - ref)) <= 1e-14
