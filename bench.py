@@ -119,6 +119,10 @@ def run_ensemble(args):
     torch.cuda.synchronize()
     t_m = time.perf_counter() - t0
     zmean128 = zspec[:64].mean(0).cpu().tolist()
+    t0 = time.perf_counter()
+    sf2 = E.structure_functions(uhs, 16, 2.0)
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
     # distance between the 1-point marginals of the two halves of the 128^3 group
     phys = torch.stack(E.inverse(uhs)[:64])
     torch.cuda.synchronize()
@@ -153,7 +157,9 @@ def run_ensemble(args):
         "statistics": {"enstrophy_spectra_ms": t_z * 1e3, "moments_128_ms": t_m * 1e3,
                        "rms_of_mean_128": float(mom_mean.pow(2).mean().sqrt().item()),
                        "mean_of_variance_128": float(mom_var.mean().item()),
-                       "w1_halves_128_ms": t_w * 1e3, "w1_halves_128_mean": w1_mean.cpu().tolist()},
+                       "w1_halves_128_ms": t_w * 1e3, "w1_halves_128_mean": w1_mean.cpu().tolist(),
+                       "structure_functions_ms": t_s * 1e3,
+                       "mean_S2_128": sf2[:64].mean(0).cpu().tolist()},
         "schedule": E.tune_report(),
     }
     print(json.dumps(out))

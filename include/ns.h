@@ -198,6 +198,15 @@ ns_status ns_enstrophy_spectrum(ns_ctx* ctx, const void* const* uhat, double* Z_
  * [3][N][N][N], overwritten.  Uses the size group's workspaces. */
 ns_status ns_moments(ns_ctx* ctx, const void* const* uhat, int32_t n, double* mean_dev, double* var_dev);
 
+/* Longitudinal velocity structure functions of order p (the structure-
+ * function writers of Sec. 2.4; reading: increments of each component along
+ * its own axis, averaged over the three axes):
+ *   S[i][l-1] = 1/3 sum_d mean_x |u_d(x + l h e_d) - u_d(x)|^p, l = 1..lmax,
+ * for u = F^-1[T uhat_i] on the sample's grid (spacing h = 2 pi / N).
+ * S_dev: device doubles [nsamples][lmax]; 1 <= lmax <= N/2 for every
+ * sample, p > 0.  Deterministic; uses the group's workspaces. */
+ns_status ns_structure_functions(ns_ctx* ctx, const void* const* uhat, int32_t lmax, double p, double* S_dev);
+
 /* Distance between the 1-point marginals of two ensembles (the statistic of
  * the paper's convergence study, Sec. 6.1): for each velocity component and
  * grid point, the 1-D Wasserstein-1 distance W1 = integral |F_a - F_b| dt

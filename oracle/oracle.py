@@ -242,6 +242,20 @@ def moments(uhs, n: int):
     return mean, var
 
 
+def structure_functions(uh: np.ndarray, n: int, lmax: int, p: float) -> np.ndarray:
+    """Longitudinal velocity structure functions of order p (the structure-
+    function writers of Sec. 2.4; reading: increments of each component
+    along its own axis, averaged over the three axes):
+    S_p(l) = 1/3 sum_d mean_x |u_d(x + l h e_d) - u_d(x)|^p, h = 2 pi / n,
+    l = 1..lmax, for u = F^-1[u-hat] on the n grid."""
+    u = inverse(uh, n)  # [c][z][y][x]
+    axis = {0: 2, 1: 1, 2: 0}  # component d varies along array axis
+    S = np.zeros(lmax)
+    for l in range(1, lmax + 1):
+        S[l - 1] = sum(np.mean(np.abs(np.roll(u[d], -l, axis=axis[d]) - u[d]) ** p) for d in range(3)) / 3.0
+    return S
+
+
 def wasserstein1_pointwise(a: np.ndarray, b: np.ndarray) -> np.ndarray:
     """1-D Wasserstein-1 distance between the empirical distributions of
     a[:, i] (na samples) and b[:, i] (nb samples) at every position i:

@@ -379,6 +379,65 @@ hipError_t launch_w1(bool f64, const void* a, int na, const void* b, int nb, lon
     return hipGetLastError();
 }
 
+// Longitudinal structure functions of a physical field u [3][N][N][N]
+// (x fastest): for shift l = blockIdx.y + 1, block x sums |u_d(x + l e_d) -
+// u_d(x)|^p over its strided share of the points and the three axes into
+// part[(l - 1) nblk + x]; k_sfun_final adds the nblk partial sums of each l
+// in order.  Both orders are fixed, so the result is deterministic.
+template <typename R>
+__global__ void __launch_bounds__(256) k_sfun(const R* __restrict__ u, int N, double p, double* part)
+{
+    __shared__ double red[256];
+    const int l = blockIdx.y + 1;
+    const long long n3 = (long long)N * N * N, plane = (long long)N * N;
+    double acc = 0.0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n3; i += (long long)gridDim.x * 256) {
+        const int x = (int)(i % N), y = (int)((i / N) % N), z = (int)(i / plane);
+        const long long ix = i - x + (x + l) % N;
+        const long long iy = i + (long long)(((y + l) % N) - y) * N;
+        const long long iz = i + (long long)(((z + l) % N) - z) * plane;
+        acc += pow(fabs((double)u[ix] - (double)u[i]), p);
+        acc += pow(fabs((double)u[n3 + iy] - (double)u[n3 + i]), p);
+        acc += pow(fabs((double)u[2 * n3 + iz] - (double)u[2 * n3 + i]), p);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long long)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ void k_sfun_final(const double* __restrict__ part, int nblk, int lmax, double scale, double* S)
+{
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= lmax) return;
+    double acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc += part[(long long)l * nblk + b];
+    S[l] = acc * scale;
+}
+
+int sfun_blocks(int N)
+{
+    const long long n3 = (long long)N * N * N;
+    const long long b = (n3 + 255) / 256;
+    return (int)(b < 1024 ? b : 1024);
+}
+
+hipError_t launch_sfun(bool f64, const void* u, int N, int lmax, double p, double* part, double* S, hipStream_t s)
+{
+    if (lmax <= 0) return hipSuccess;
+    const int nblk = sfun_blocks(N);
+    if (f64) hipLaunchKernelGGL(k_sfun<double>, dim3(nblk, lmax), dim3(256), 0, s, (const double*)u, N, p, part);
+    else hipLaunchKernelGGL(k_sfun<float>, dim3(nblk, lmax), dim3(256), 0, s, (const float*)u, N, p, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sfun_final, dim3((lmax + 63) / 64), dim3(64), 0, s, part, nblk, lmax,
+                       1.0 / (3.0 * (double)N * N * N), S);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_random(bool f64, void* p, long long nreal, unsigned long long seed, hipStream_t s)
 {
     if (nreal <= 0) return hipSuccess;

@@ -15,6 +15,10 @@ hipError_t launch_scale(double* p, double a, long long n, hipStream_t s);
 // pointwise 1-D Wasserstein-1 distance of two sample sets [na][npts] and
 // [nb][npts] into w [npts]; mean (if non-null) [ncomp] = mean of each of the
 // ncomp equal parts of w; fails if na + nb exceeds 20480
+// longitudinal structure functions S[l - 1], l = 1..lmax, of a physical
+// field [3][N^3]; part: sfun_blocks(N) * lmax doubles of scratch
+int sfun_blocks(int N);
+hipError_t launch_sfun(bool f64, const void* u, int N, int lmax, double p, double* part, double* S, hipStream_t s);
 hipError_t launch_w1(bool f64, const void* a, int na, const void* b, int nb, long long npts, int ncomp, double* w,
                      double* mean, hipStream_t s);
 hipError_t launch_fill(double* p, double v, int n, hipStream_t s);

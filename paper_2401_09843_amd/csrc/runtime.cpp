@@ -1236,6 +1236,28 @@ ns_status ns_adjoint_steps(ns_ctx* c, const void* const* tape, int32_t nsteps, c
     return NS_OK;
 }
 
+ns_status ns_structure_functions(ns_ctx* c, const void* const* uh, int32_t lmax, double p, double* S)
+{
+    CHECK_STATE(c);
+    ns_status st;
+    if ((st = check_ptrs(c, uh, "uhat"))) return st;
+    if (!S || !(p > 0) || !std::isfinite(p)) return fail(c, NS_ERR_ARG, "S must be non-null and p finite and > 0");
+    for (size_t i = 0; i < c->n.size(); ++i) {
+        Group& g = c->groups[c->group_of[i]];
+        if (lmax < 1 || lmax > g.N / 2) return fail(c, NS_ERR_ARG, "lmax = %d must lie in 1..%d", lmax, g.N / 2);
+        // the partial sums go to A, free once the field is in C
+        const size_t need = sizeof(double) * (size_t)sfun_blocks(g.N) * lmax;
+        if (need > cwb(c) * 6ULL * g.N * g.MMx * g.B)
+            return fail(c, NS_ERR_ARG, "lmax = %d needs more scratch than the workspace holds", lmax);
+    }
+    for (size_t i = 0; i < c->n.size(); ++i) {
+        Group& g = c->groups[c->group_of[i]];
+        if ((st = inverse_one(c, g, uh[i], g.C))) return st;
+        HIP_TRY(c, launch_sfun(c->f64, g.C, g.N, lmax, p, (double*)g.A, S + i * (size_t)lmax, c->stream));
+    }
+    return NS_OK;
+}
+
 ns_status ns_wasserstein1(ns_ctx* c, const void* a, int32_t na, const void* b, int32_t nb, int32_t n, double* w,
                           double* mean)
 {

@@ -23,7 +23,8 @@ NS_USE_GRAPH, NS_CHECK_FINITE, NS_NO_TUNE, NS_NO_FUSE, NS_FUSE, NS_PAD = 1, 2, 4
 # every symbol the header declares
 EXPORTS = ("ns_init", "ns_destroy", "ns_last_error", "ns_workspace_bytes", "ns_supported_sizes", "ns_forward",
            "ns_inverse", "ns_project", "ns_rhs", "ns_step", "ns_tape_bytes", "ns_step_taped", "ns_adjoint_step", "ns_adjoint_steps",
-           "ns_energy_spectrum", "ns_enstrophy_spectrum", "ns_moments", "ns_wasserstein1", "ns_sync", "ns_profile", "ns_profile_read",
+           "ns_energy_spectrum", "ns_enstrophy_spectrum", "ns_moments", "ns_structure_functions",
+           "ns_wasserstein1", "ns_sync", "ns_profile", "ns_profile_read",
            "ns_variant_count", "ns_set_variant", "ns_tune_report")
 NS_NPASS = 5
 PASS_NAMES = ("I1_inv_z", "I2_inv_y", "X_c2r_prod_r2c", "F2_fwd_y", "F3_fwd_z_epilogue")
@@ -73,6 +74,7 @@ def lib() -> ctypes.CDLL:
             "ns_enstrophy_spectrum": [P, PP, P, I32],
             "ns_moments": [P, PP, I32, P, P],
             "ns_wasserstein1": [P, P, I32, P, I32, I32, P, P],
+            "ns_structure_functions": [P, PP, I32, D, P],
             "ns_sync": [P],
             "ns_profile": [P, I32],
             "ns_profile_read": [P, PD, ctypes.POINTER(ctypes.c_int64)],
@@ -281,6 +283,15 @@ class Solver:
         self._check(self._L.ns_moments(self._ctx, _ptrs(xs), int(n), ctypes.c_void_p(mean.data_ptr()),
                                        ctypes.c_void_p(var.data_ptr())))
         return mean, var
+
+    def structure_functions(self, uhat, lmax: int, p: float):
+        """Longitudinal structure functions of order p for shifts 1..lmax
+        grid points: float64 [nsamples, lmax]."""
+        xs = self._spec(self._list(uhat))
+        S = torch.empty((len(xs), lmax), dtype=torch.float64, device=self.device)
+        self._check(self._L.ns_structure_functions(self._ctx, _ptrs(xs), int(lmax), float(p),
+                                                   ctypes.c_void_p(S.data_ptr())))
+        return S
 
     def wasserstein1(self, a: torch.Tensor, b: torch.Tensor):
         """Pointwise W1 between the 1-point marginals (component by

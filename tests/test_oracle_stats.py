@@ -65,3 +65,25 @@ def test_wasserstein_matches_scipy(orc):
     got = orc.wasserstein1_pointwise(a, b)
     ref = np.array([wasserstein_distance(a[:, i], b[:, i]) for i in range(40)])
     assert np.max(np.abs(got - ref)) <= 1e-14
+
+
+def test_structure_functions_of_a_sine(orc):
+    """u = (sin kX, 0, 0): the increment along x is 2 cos(kX + a) sin a with
+    a = pi k l / n, so S_2 = (2/3) sin^2 a and S_4 = 2 sin^4 a (grid means of
+    cos^2 and cos^4 are 1/2 and 3/8 when n does not divide 4k)."""
+    n, k = 16, 3
+    X, Y, Z = inputs.grid(n)
+    u = np.stack([np.sin(k * X), 0 * X, 0 * X])
+    uh = orc.forward(u)
+    l = np.arange(1, 9)
+    a = np.pi * k * l / n
+    assert np.max(np.abs(orc.structure_functions(uh, n, 8, 2.0) - 2.0 / 3.0 * np.sin(a) ** 2)) <= 1e-14
+    assert np.max(np.abs(orc.structure_functions(uh, n, 8, 4.0) - 2.0 * np.sin(a) ** 4)) <= 1e-14
+
+
+def test_structure_functions_symmetry(orc):
+    """A shift by l and by n - l average the same increments."""
+    n = 12
+    uh = orc.forward(inputs.random_field(n, seed=4))
+    S = orc.structure_functions(uh, n, n - 1, 1.5)
+    assert np.max(np.abs(S - S[::-1])) <= 1e-14 * S.max()
