@@ -57,19 +57,31 @@ constexpr double kS16[16] = {0.0, 0.38268343236508977173, 0.70710678118654752440
                                         0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
                                         -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
 
-// a * exp(DIR 2 pi i e / RR) for a compile-time exponent, RR dividing 16
+// cos and sin of 2 pi j / 12 (sqrt(3)/2 and 1/2 up to sign)
+constexpr double kC12[12] = {1.0, 0.86602540378443864676, 0.5, 0.0, -0.5, -0.86602540378443864676,
+                             -1.0, -0.86602540378443864676, -0.5, 0.0, 0.5, 0.86602540378443864676};
+constexpr double kS12[12] = {0.0, 0.5, 0.86602540378443864676, 1.0, 0.86602540378443864676, 0.5,
+                             0.0, -0.5, -0.86602540378443864676, -1.0, -0.86602540378443864676, -0.5};
+
+// a * exp(DIR 2 pi i e / RR) for a compile-time exponent, RR dividing 16 or 12
 template <int RR, int E, int DIR, typename R>
 __device__ __forceinline__ cpx<R> rot_const(cpx<R> a)
 {
+    static_assert(16 % RR == 0 || 12 % RR == 0, "constant rotations for orders dividing 16 or 12");
     constexpr int e = E % RR;
     if constexpr (e == 0) return a;
     else if constexpr (4 * e == RR) return mul_i<DIR>(a);
     else if constexpr (2 * e == RR) return {-a.x, -a.y};
     else if constexpr (4 * e == 3 * RR) return mul_i<-DIR>(a);
-    else {
+    else if constexpr (16 % RR == 0) {
         constexpr int j = e * (16 / RR);
         const R c = (R)kC16[j];
         const R s = (R)(DIR * kS16[j]);
+        return {a.x * c - a.y * s, a.x * s + a.y * c};
+    } else {
+        constexpr int j = e * (12 / RR);
+        const R c = (R)kC12[j];
+        const R s = (R)(DIR * kS12[j]);
         return {a.x * c - a.y * s, a.x * s + a.y * c};
     }
 }
@@ -186,6 +198,16 @@ struct Dft<8, DIR, T> {
 template <int DIR, typename T>
 struct Dft<16, DIR, T> {
     __device__ __forceinline__ static void run(cpx<T>* v) { DftSplit<4, 4, DIR, T>::run(v); }
+};
+
+template <int DIR, typename T>
+struct Dft<6, DIR, T> {
+    __device__ __forceinline__ static void run(cpx<T>* v) { DftSplit<2, 3, DIR, T>::run(v); }
+};
+
+template <int DIR, typename T>
+struct Dft<12, DIR, T> {
+    __device__ __forceinline__ static void run(cpx<T>* v) { DftSplit<4, 3, DIR, T>::run(v); }
 };
 
 // ---------------------------------------------------------------- helpers

@@ -140,3 +140,32 @@ def test_padded_rejects_unsupported_mode_counts(ns):
     for n in (30, 7, 2048):
         with pytest.raises(ns.NSError):
             ns.Solver(n, pad=True)
+
+
+@pytest.mark.parametrize("n,dtype,tol", [(256, torch.float64, 1e-12), (512, torch.float32, 1e-5),
+                                         (1024, torch.float32, 1e-5)])
+def test_padded_variants_full_size(ns, orc, n, dtype, tol):
+    """Every schedule variant of every pass at the padded grids (radix-3, 6
+    and 12 plans), one at a time, on a sparse field with modes on the cutoff
+    edges, against the triad sum."""
+    K = n // 2 - 1
+    modes, coefs = inputs.sparse_modes(n, seed=n + 33, count=12, kmax=K)
+    kout = _support(modes, K)
+    ref = orc.rhs_sparse(modes, coefs, kout, n, orc.Params(kcut=K))
+    cd = torch.complex128 if dtype == torch.float64 else torch.complex64
+    S = ns.Solver(n, dtype=dtype, graph=False, pad=True)
+    uh = torch.zeros((3, n, n, n // 2 + 1), dtype=cd, device="cuda")
+    sel = modes[:, 0] >= 0
+    for c in range(3):
+        uh[c, torch.as_tensor(modes[sel, 2] % n), torch.as_tensor(modes[sel, 1] % n),
+           torch.as_tensor(modes[sel, 0])] = torch.as_tensor(coefs[sel, c]).to(cd).cuda()
+    oz, oy, ox = (torch.as_tensor(kout[:, 2] % n), torch.as_tensor(kout[:, 1] % n), torch.as_tensor(kout[:, 0]))
+    for p in range(5):
+        for v in range(S.variant_count(n, p)):
+            S.set_variant(n, p, v)
+            print("padded n=%d pass %d variant %d" % (n, p, v), flush=True)
+            F = S.rhs(uh)
+            got = torch.stack([F[c, oz, oy, ox] for c in range(3)], dim=1).cpu().numpy().astype(np.complex128)
+            del F
+            assert rel(got, ref) <= tol, (p, v)
+        S.set_variant(n, p, 0)
