@@ -192,7 +192,9 @@ ns_status ns_enstrophy_spectrum(ns_ctx* ctx, const void* const* uhat, double* Z_
 /* Pointwise statistics of the empirical measure of Algorithm 1 (step 3)
  * over the samples of size n: with u_b = F^-1[T uhat_b] on the sample grid
  * (N = n, or 3n/2 with NS_PAD), mean = (1/B) sum_b u_b and var = (1/B)
- * sum_b (u_b - mean)^2, accumulated in FP64 in sample order (deterministic).
+ * sum_b (u_b - mean)^2, accumulated in FP64 in sample order (deterministic):
+ * the group's samples go back to the grid in batched passes, then one
+ * Welford pass per point.
  * uhat: host array [nsamples] as for every call (samples of other sizes are
  * not read); mean_dev and var_dev: distinct device arrays of doubles
  * [3][N][N][N], overwritten.  Uses the size group's workspaces. */

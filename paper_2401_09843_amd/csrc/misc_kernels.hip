@@ -255,43 +255,31 @@ hipError_t launch_spectrum(bool f64, const void* u, double* E, int N, int K, int
     return hipGetLastError();
 }
 
-// One sample of a streaming mean / second moment (Welford): with k the
-// sample's 1-based index, d = x - mean; mean += d / k; m2 += d (x - mean).
-// Applied in sample order the result is deterministic.
+// Pointwise mean and variance (1/B) over B samples x[b * n + i]: a Welford
+// update per sample in sample order (d = v - mean; mean += d / k;
+// m2 += d (v - mean)), in FP64, so the result is deterministic.
 template <typename R>
-__global__ void k_welford(const R* __restrict__ x, double* mean, double* m2, long long n, int k)
+__global__ void k_moments(const R* __restrict__ x, int B, long long n, double* __restrict__ mean,
+                          double* __restrict__ var)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double v = (double)x[i];
-    const double d = v - mean[i];
-    const double mu = mean[i] + d / (double)k;
-    mean[i] = mu;
-    m2[i] += d * (v - mu);
-}
-
-__global__ void k_scale(double* p, double a, long long n)
-{
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] *= a;
-}
-
-hipError_t launch_welford(bool f64, const void* x, double* mean, double* m2, long long n, int k, hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    if (k == 1) {  // start from zero
-        hipLaunchKernelGGL(k_fill, dim3(nblocks(n, 256)), dim3(256), 0, s, mean, 0.0, n);
-        hipLaunchKernelGGL(k_fill, dim3(nblocks(n, 256)), dim3(256), 0, s, m2, 0.0, n);
+    double mu = 0.0, m2 = 0.0;
+    for (int b = 0; b < B; ++b) {
+        const double v = (double)x[(long long)b * n + i];
+        const double d = v - mu;
+        mu += d / (double)(b + 1);
+        m2 += d * (v - mu);
     }
-    if (f64) hipLaunchKernelGGL(k_welford<double>, dim3(nblocks(n, 256)), dim3(256), 0, s, (const double*)x, mean, m2, n, k);
-    else hipLaunchKernelGGL(k_welford<float>, dim3(nblocks(n, 256)), dim3(256), 0, s, (const float*)x, mean, m2, n, k);
-    return hipGetLastError();
+    mean[i] = mu;
+    var[i] = m2 / (double)B;
 }
 
-hipError_t launch_scale(double* p, double a, long long n, hipStream_t s)
+hipError_t launch_moments(bool f64, const void* x, int B, long long n, double* mean, double* var, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scale, dim3(nblocks(n, 256)), dim3(256), 0, s, p, a, n);
+    if (n <= 0 || B <= 0) return hipSuccess;
+    if (f64) hipLaunchKernelGGL(k_moments<double>, dim3(nblocks(n, 256)), dim3(256), 0, s, (const double*)x, B, n, mean, var);
+    else hipLaunchKernelGGL(k_moments<float>, dim3(nblocks(n, 256)), dim3(256), 0, s, (const float*)x, B, n, mean, var);
     return hipGetLastError();
 }
 

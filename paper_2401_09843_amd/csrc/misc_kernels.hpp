@@ -8,10 +8,8 @@ hipError_t launch_unpack(bool f64, const void* compact, void* r2c, int N, int K,
 hipError_t launch_project(bool f64, void* r2c, int N, int K, hipStream_t s);
 // kind 0: energy spectrum, 1: enstrophy spectrum
 hipError_t launch_spectrum(bool f64, const void* r2c, double* E, int N, int K, int kbins, hipStream_t s, int kind = 0);
-// streaming mean / second moment over samples (k = 1-based sample index;
-// k = 1 clears mean and m2 first), and p *= a
-hipError_t launch_welford(bool f64, const void* x, double* mean, double* m2, long long n, int k, hipStream_t s);
-hipError_t launch_scale(double* p, double a, long long n, hipStream_t s);
+// pointwise mean and variance (1/B) of B samples [B][n], FP64, sample order
+hipError_t launch_moments(bool f64, const void* x, int B, long long n, double* mean, double* var, hipStream_t s);
 // pointwise 1-D Wasserstein-1 distance of two sample sets [na][npts] and
 // [nb][npts] into w [npts]; mean (if non-null) [ncomp] = mean of each of the
 // ncomp equal parts of w; fails if na + nb exceeds 20480

@@ -8,7 +8,9 @@
 //   F2  forward C2C along y, keep the M retained rows   (k_colfft, COL_FWD_TRUNC)
 //   F3  forward C2C along z of the six products, then -i k.B-hat, the Leray
 //       projection (eq. (2.5)), hyperviscosity (eqs. (2.1)-(2.3)) and the
-//       SSP-RK3 stage combination (eq. (2.6))            (k_f3, F3_RHS)
+//       SSP-RK3 stage combination (eq. (2.6))            (k_f3, F3_RHS);
+//       its fused form (ZI = 1) also runs the next stage's I1 on the new
+//       state while it is in registers
 //
 // Strided axes are transformed by tiles of T neighbouring columns: each
 // thread loads whole rows of T columns (coalesced) straight into registers,

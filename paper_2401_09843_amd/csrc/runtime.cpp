@@ -1,6 +1,7 @@
 // Host runtime behind the C ABI of include/ns.h: contexts, sample groups,
 // workspaces, twiddle and damping tables, the pass sequence of one
-// right-hand-side evaluation, SSP-RK3 stages and hipGraph replay.
+// right-hand-side evaluation, SSP-RK3 stages (plain or fused) and hipGraph
+// replay, the autotuner, the adjoint, and the in-situ statistics.
 #include "../../include/ns.h"
 
 #include <hip/hip_runtime.h>
@@ -1063,16 +1064,22 @@ ns_status ns_moments(ns_ctx* c, const void* const* uh, int32_t n, double* mean, 
     ns_status st;
     if ((st = check_ptrs(c, uh, "uhat"))) return st;
     if (!mean || !var || mean == var) return fail(c, NS_ERR_ARG, "mean and var must be distinct non-null device arrays");
-    Group* g = group_of_size(c, n);
-    if (!g) return fail(c, NS_ERR_ARG, "no samples of size %d", n);
-    const long long np = 3LL * g->N * g->N * g->N;
-    // each sample's physical field goes to C (4 N^3 reals or more), then one
-    // streaming update in sample order
-    for (int b = 0; b < g->B; ++b) {
-        if ((st = inverse_one(c, *g, uh[g->samples[b]], g->C))) return st;
-        HIP_TRY(c, launch_welford(c->f64, g->C, mean, var, np, b + 1, c->stream));
-    }
-    HIP_TRY(c, launch_scale(var, 1.0 / g->B, np, c->stream));
+    Group* gp = group_of_size(c, n);
+    if (!gp) return fail(c, NS_ERR_ARG, "no samples of size %d", n);
+    Group& g = *gp;
+    const long long N = g.N, B = g.B, Mx = g.Mx;
+    hipStream_t s = c->stream;
+    // the whole group back to its grid in three batched passes: compact
+    // states in U1, I1 and I2 as in a right-hand side, then the C2R of all
+    // samples into C ([B][3][N^3] reals; C holds 4 N^3 B or more)
+    for (int b = 0; b < g.B; ++b)
+        HIP_TRY(c, launch_pack(c->f64, uh[g.samples[b]], (char*)g.U1 + cwb(c) * g.st * b, g.L, g.K, s));
+    const PassArgs a = pass_args(g, g.U1, nullptr, nullptr, 0.0, 0.0, 0.0, g.dt);
+    HIP_TRY(c, launch_pass(g, 0, g.sel[0], a, s));
+    HIP_TRY(c, launch_pass(g, 1, g.sel[1], a, s));
+    XArgs ax{g.Bw, g.C, g.tw, B * N * N / 2, N * N * Mx, N * N * N, 3 * N * N * Mx, 3 * N * N * N, g.K, 1.0};
+    HIP_TRY(c, g.kern->x_inv3(ax, s));
+    HIP_TRY(c, launch_moments(c->f64, g.C, g.B, 3LL * N * N * N, mean, var, s));
     return NS_OK;
 }
 

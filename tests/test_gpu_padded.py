@@ -142,8 +142,8 @@ def test_padded_rejects_unsupported_mode_counts(ns):
             ns.Solver(n, pad=True)
 
 
-@pytest.mark.parametrize("n,dtype,tol", [(256, torch.float64, 1e-12), (512, torch.float32, 1e-5),
-                                         (1024, torch.float32, 1e-5)])
+@pytest.mark.parametrize("n,dtype,tol", [(128, torch.float32, 1e-5), (256, torch.float64, 1e-12),
+                                         (512, torch.float32, 1e-5), (1024, torch.float32, 1e-5)])
 def test_padded_variants_full_size(ns, orc, n, dtype, tol):
     """Every schedule variant of every pass at the padded grids (radix-3, 6
     and 12 plans), one at a time, on a sparse field with modes on the cutoff
