@@ -82,6 +82,12 @@ def run_ensemble(args):
     E.step(uhs, dts, steps)
     torch.cuda.synchronize()
     t_batched = time.perf_counter() - t0
+    if args.batched_only:  # the batched steps alone (for a kernel trace)
+        print(json.dumps({"metric": "ensemble samples/s (96 samples: 64x128^3 + 32x64^3, 200 SSP-RK3 steps)",
+                          "value": len(sizes) / (t_batched * 200.0 / steps), "unit": "samples/s", "n_gpus": 1,
+                          "steps": steps, "warmup": args.warmup, "ms_per_step": t_batched / steps * 1e3,
+                          "family": args.family, "batched_only": True, "schedule": E.tune_report()}))
+        return
     # looping the plain solver (one context per grid size, one sample at a time)
     # with the schedules the ensemble runs, so that both compute the same bits
     form = {r["N"]: r["fused"] for r in E.tune_report() if r["pass"] == "F3_fwd_z_epilogue"}
@@ -222,6 +228,8 @@ def main():
                     help="Algorithm 2 in its padded form: --n modes per axis, passes on the 3n/2 grid")
     ap.add_argument("--print-source-hash", action="store_true")
     ap.add_argument("--ensemble", action="store_true", help="run the 96-sample ensemble workload instead")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="with --ensemble: time the batched steps only (no looped solvers, no statistics)")
     ap.add_argument("--family", default="shear", choices=["shear", "tg", "cyl"],
                     help="initial data of the ensemble: shear layers, or the paper's perturbed Taylor-Green "
                          "vortices or cylindrical shear flows")
