@@ -367,26 +367,43 @@ hipError_t launch_w1(bool f64, const void* a, int na, const void* b, int nb, lon
     return hipGetLastError();
 }
 
-// Longitudinal structure functions of a physical field u [3][N][N][N]
-// (x fastest): for shift l = blockIdx.y + 1, block x sums |u_d(x + l e_d) -
-// u_d(x)|^p over its strided share of the points and the three axes into
-// part[(l - 1) nblk + x]; k_sfun_final adds the nblk partial sums of each l
-// in order.  Both orders are fixed, so the result is deterministic.
-template <typename R>
+// Longitudinal structure functions of B physical fields u [B][3][N][N][N]
+// (x fastest): for shift l = blockIdx.y + 1 and sample b = blockIdx.z, block
+// x sums |u_d(x + l e_d) - u_d(x)|^p over its strided share of the points
+// and the three axes into part[(b lmax + l - 1) nblk + x]; k_sfun_final adds
+// the nblk partial sums of each (b, l) in order.  Both orders are fixed, so
+// the result is deterministic.  IP > 0: the integer power p = IP by
+// multiplication; IP = 0: pow.
+template <int IP>
+__device__ __forceinline__ double abs_pow(double d, double p)
+{
+    if constexpr (IP == 0) {
+        return pow(fabs(d), p);
+    } else {
+        const double a = fabs(d);
+        double r = a;
+#pragma unroll
+        for (int k = 1; k < IP; ++k) r *= a;
+        return r;
+    }
+}
+
+template <typename R, int IP>
 __global__ void __launch_bounds__(256) k_sfun(const R* __restrict__ u, int N, double p, double* part)
 {
     __shared__ double red[256];
     const int l = blockIdx.y + 1;
     const long long n3 = (long long)N * N * N, plane = (long long)N * N;
+    const R* ub = u + (long long)blockIdx.z * 3 * n3;
     double acc = 0.0;
     for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n3; i += (long long)gridDim.x * 256) {
         const int x = (int)(i % N), y = (int)((i / N) % N), z = (int)(i / plane);
         const long long ix = i - x + (x + l) % N;
         const long long iy = i + (long long)(((y + l) % N) - y) * N;
         const long long iz = i + (long long)(((z + l) % N) - z) * plane;
-        acc += pow(fabs((double)u[ix] - (double)u[i]), p);
-        acc += pow(fabs((double)u[n3 + iy] - (double)u[n3 + i]), p);
-        acc += pow(fabs((double)u[2 * n3 + iz] - (double)u[2 * n3 + i]), p);
+        acc += abs_pow<IP>((double)ub[ix] - (double)ub[i], p);
+        acc += abs_pow<IP>((double)ub[n3 + iy] - (double)ub[n3 + i], p);
+        acc += abs_pow<IP>((double)ub[2 * n3 + iz] - (double)ub[2 * n3 + i], p);
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -394,7 +411,8 @@ __global__ void __launch_bounds__(256) k_sfun(const R* __restrict__ u, int N, do
         if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[(long long)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+    if (threadIdx.x == 0)
+        part[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
 }
 
 __global__ void k_sfun_final(const double* __restrict__ part, int nblk, int lmax, double scale, double* S)
@@ -413,15 +431,33 @@ int sfun_blocks(int N)
     return (int)(b < 1024 ? b : 1024);
 }
 
-hipError_t launch_sfun(bool f64, const void* u, int N, int lmax, double p, double* part, double* S, hipStream_t s)
+template <typename R>
+static void sfun_dispatch(const R* u, int N, int lmax, int B, double p, double* part, hipStream_t s)
 {
-    if (lmax <= 0) return hipSuccess;
-    const int nblk = sfun_blocks(N);
-    if (f64) hipLaunchKernelGGL(k_sfun<double>, dim3(nblk, lmax), dim3(256), 0, s, (const double*)u, N, p, part);
-    else hipLaunchKernelGGL(k_sfun<float>, dim3(nblk, lmax), dim3(256), 0, s, (const float*)u, N, p, part);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sfun_final, dim3((lmax + 63) / 64), dim3(64), 0, s, part, nblk, lmax,
+    const dim3 grid(sfun_blocks(N), lmax, B);
+    const int ip = (p == (double)(int)p && p >= 1 && p <= 6) ? (int)p : 0;
+    switch (ip) {
+        case 1: hipLaunchKernelGGL((k_sfun<R, 1>), grid, dim3(256), 0, s, u, N, p, part); break;
+        case 2: hipLaunchKernelGGL((k_sfun<R, 2>), grid, dim3(256), 0, s, u, N, p, part); break;
+        case 3: hipLaunchKernelGGL((k_sfun<R, 3>), grid, dim3(256), 0, s, u, N, p, part); break;
+        case 4: hipLaunchKernelGGL((k_sfun<R, 4>), grid, dim3(256), 0, s, u, N, p, part); break;
+        case 5: hipLaunchKernelGGL((k_sfun<R, 5>), grid, dim3(256), 0, s, u, N, p, part); break;
+        case 6: hipLaunchKernelGGL((k_sfun<R, 6>), grid, dim3(256), 0, s, u, N, p, part); break;
+        default: hipLaunchKernelGGL((k_sfun<R, 0>), grid, dim3(256), 0, s, u, N, p, part); break;
+    }
+}
+
+hipError_t launch_sfun(bool f64, const void* u, int N, int lmax, int B, double p, double* part, hipStream_t s)
+{
+    if (lmax <= 0 || B <= 0) return hipSuccess;
+    if (f64) sfun_dispatch((const double*)u, N, lmax, B, p, part, s);
+    else sfun_dispatch((const float*)u, N, lmax, B, p, part, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_sfun_final(const double* part, int N, int lmax, double* S, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sfun_final, dim3((lmax + 63) / 64), dim3(64), 0, s, part, sfun_blocks(N), lmax,
                        1.0 / (3.0 * (double)N * N * N), S);
     return hipGetLastError();
 }

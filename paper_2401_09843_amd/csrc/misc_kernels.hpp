@@ -13,10 +13,13 @@ hipError_t launch_moments(bool f64, const void* x, int B, long long n, double* m
 // pointwise 1-D Wasserstein-1 distance of two sample sets [na][npts] and
 // [nb][npts] into w [npts]; mean (if non-null) [ncomp] = mean of each of the
 // ncomp equal parts of w; fails if na + nb exceeds 20480
-// longitudinal structure functions S[l - 1], l = 1..lmax, of a physical
-// field [3][N^3]; part: sfun_blocks(N) * lmax doubles of scratch
+// longitudinal structure functions of B physical fields [B][3][N^3]: partial
+// sums into part (B * lmax * sfun_blocks(N) doubles), then per sample b
+// launch_sfun_final(part + b * lmax * sfun_blocks(N), ...) writes S[l - 1],
+// l = 1..lmax
 int sfun_blocks(int N);
-hipError_t launch_sfun(bool f64, const void* u, int N, int lmax, double p, double* part, double* S, hipStream_t s);
+hipError_t launch_sfun(bool f64, const void* u, int N, int lmax, int B, double p, double* part, hipStream_t s);
+hipError_t launch_sfun_final(const double* part, int N, int lmax, double* S, hipStream_t s);
 hipError_t launch_w1(bool f64, const void* a, int na, const void* b, int nb, long long npts, int ncomp, double* w,
                      double* mean, hipStream_t s);
 hipError_t launch_fill(double* p, double v, int n, hipStream_t s);

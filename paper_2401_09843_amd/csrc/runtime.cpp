@@ -1048,6 +1048,23 @@ static ns_status inverse_one(ns_ctx* c, Group& g, const void* uh, void* u)
     return NS_OK;
 }
 
+// The physical fields of every sample of group g into C ([B][3][N^3]
+// reals; C holds 4 N^3 B or more) in three batched passes: compact states
+// in U1, I1 and I2 as in a right-hand side, then the C2R of all samples.
+static ns_status group_to_grid(ns_ctx* c, Group& g, const void* const* uh)
+{
+    const long long N = g.N, B = g.B, Mx = g.Mx;
+    hipStream_t s = c->stream;
+    for (int b = 0; b < g.B; ++b)
+        HIP_TRY(c, launch_pack(c->f64, uh[g.samples[b]], (char*)g.U1 + cwb(c) * g.st * b, g.L, g.K, s));
+    const PassArgs a = pass_args(g, g.U1, nullptr, nullptr, 0.0, 0.0, 0.0, g.dt);
+    HIP_TRY(c, launch_pass(g, 0, g.sel[0], a, s));
+    HIP_TRY(c, launch_pass(g, 1, g.sel[1], a, s));
+    XArgs ax{g.Bw, g.C, g.tw, B * N * N / 2, N * N * Mx, N * N * N, 3 * N * N * Mx, 3 * N * N * N, g.K, 1.0};
+    HIP_TRY(c, g.kern->x_inv3(ax, s));
+    return NS_OK;
+}
+
 ns_status ns_inverse(ns_ctx* c, const void* const* uh, void* const* u)
 {
     CHECK_STATE(c);
@@ -1067,19 +1084,9 @@ ns_status ns_moments(ns_ctx* c, const void* const* uh, int32_t n, double* mean, 
     Group* gp = group_of_size(c, n);
     if (!gp) return fail(c, NS_ERR_ARG, "no samples of size %d", n);
     Group& g = *gp;
-    const long long N = g.N, B = g.B, Mx = g.Mx;
-    hipStream_t s = c->stream;
-    // the whole group back to its grid in three batched passes: compact
-    // states in U1, I1 and I2 as in a right-hand side, then the C2R of all
-    // samples into C ([B][3][N^3] reals; C holds 4 N^3 B or more)
-    for (int b = 0; b < g.B; ++b)
-        HIP_TRY(c, launch_pack(c->f64, uh[g.samples[b]], (char*)g.U1 + cwb(c) * g.st * b, g.L, g.K, s));
-    const PassArgs a = pass_args(g, g.U1, nullptr, nullptr, 0.0, 0.0, 0.0, g.dt);
-    HIP_TRY(c, launch_pass(g, 0, g.sel[0], a, s));
-    HIP_TRY(c, launch_pass(g, 1, g.sel[1], a, s));
-    XArgs ax{g.Bw, g.C, g.tw, B * N * N / 2, N * N * Mx, N * N * N, 3 * N * N * Mx, 3 * N * N * N, g.K, 1.0};
-    HIP_TRY(c, g.kern->x_inv3(ax, s));
-    HIP_TRY(c, launch_moments(c->f64, g.C, g.B, 3LL * N * N * N, mean, var, s));
+    const long long N = g.N;
+    if ((st = group_to_grid(c, g, uh))) return st;
+    HIP_TRY(c, launch_moments(c->f64, g.C, g.B, 3LL * N * N * N, mean, var, c->stream));
     return NS_OK;
 }
 
@@ -1249,18 +1256,20 @@ ns_status ns_structure_functions(ns_ctx* c, const void* const* uh, int32_t lmax,
     ns_status st;
     if ((st = check_ptrs(c, uh, "uhat"))) return st;
     if (!S || !(p > 0) || !std::isfinite(p)) return fail(c, NS_ERR_ARG, "S must be non-null and p finite and > 0");
-    for (size_t i = 0; i < c->n.size(); ++i) {
-        Group& g = c->groups[c->group_of[i]];
+    for (Group& g : c->groups) {
         if (lmax < 1 || lmax > g.N / 2) return fail(c, NS_ERR_ARG, "lmax = %d must lie in 1..%d", lmax, g.N / 2);
-        // the partial sums go to A, free once the field is in C
-        const size_t need = sizeof(double) * (size_t)sfun_blocks(g.N) * lmax;
+        // the partial sums go to A, free once the fields are in C
+        const size_t need = sizeof(double) * (size_t)sfun_blocks(g.N) * lmax * g.B;
         if (need > cwb(c) * 6ULL * g.N * g.MMx * g.B)
             return fail(c, NS_ERR_ARG, "lmax = %d needs more scratch than the workspace holds", lmax);
     }
-    for (size_t i = 0; i < c->n.size(); ++i) {
-        Group& g = c->groups[c->group_of[i]];
-        if ((st = inverse_one(c, g, uh[i], g.C))) return st;
-        HIP_TRY(c, launch_sfun(c->f64, g.C, g.N, lmax, p, (double*)g.A, S + i * (size_t)lmax, c->stream));
+    for (Group& g : c->groups) {
+        if ((st = group_to_grid(c, g, uh))) return st;
+        double* part = (double*)g.A;
+        HIP_TRY(c, launch_sfun(c->f64, g.C, g.N, lmax, g.B, p, part, c->stream));
+        const size_t per = (size_t)sfun_blocks(g.N) * lmax;
+        for (int b = 0; b < g.B; ++b)
+            HIP_TRY(c, launch_sfun_final(part + b * per, g.N, lmax, S + (size_t)g.samples[b] * lmax, c->stream));
     }
     return NS_OK;
 }
