@@ -237,3 +237,61 @@ def test_sparse_triad_rhs_matches_pseudo_spectral(orc, n):
     ref = np.stack([full[:, c % n, b % n, a] for a, b, c in outm])
     assert np.max(np.abs(got - ref)) <= 1e-14 * max(1.0, np.max(np.abs(ref)))
     assert np.max(np.abs(ref)) > 1e-3
+
+
+# ---------------------------------------------------------------- div_rel
+# div_rel = ||(I - P) u-hat|| / ||u-hat|| (the relative size of the part the
+# Leray projection of eq. (2.5) removes).  Pinned on fields whose longitudinal
+# and transversal parts are known in physical space, so the expected values
+# come from grid means (Parseval) and not from the oracle's spectral formula.
+def _gradient_field(n):
+    # u = grad phi, phi = sin(2x + y) + cos(z - 3y): purely longitudinal
+    x, y, z = inputs.grid(n)
+    return np.stack([2 * np.cos(2 * x + y), np.cos(2 * x + y) + 3 * np.sin(z - 3 * y), -np.sin(z - 3 * y)])
+
+
+@pytest.mark.parametrize("n", [12, 16])
+def test_div_rel_of_a_gradient_is_one(orc, n):
+    g = _gradient_field(n)
+    assert abs(orc.div_rel(inputs.half_spectrum(g), n) - 1.0) <= 1e-14
+
+
+@pytest.mark.parametrize("a", [0.3, 1.0, 2.5])
+def test_div_rel_of_solenoidal_plus_gradient(orc, a):
+    # Taylor-Green is divergence-free and L2-orthogonal to any gradient on the
+    # torus, so ||(I-P)(s + a g)||^2 = a^2 mean|g|^2 and ||s + a g||^2 =
+    # mean|s|^2 + a^2 mean|g|^2
+    n = 16
+    s = inputs.taylor_green(n)
+    g = _gradient_field(n)
+    es = np.mean(np.sum(s * s, axis=0))
+    eg = np.mean(np.sum(g * g, axis=0))
+    want = np.sqrt(a * a * eg / (es + a * a * eg))
+    assert abs(orc.div_rel(inputs.half_spectrum(s + a * g), n) - want) <= 1e-14
+
+
+def test_div_rel_counts_the_mean_flow_in_the_norm_only(orc):
+    # a constant flow is divergence-free (k = 0 has no longitudinal part) but
+    # belongs to ||u||: u = c + g gives sqrt(mean|g|^2 / (|c|^2 + mean|g|^2))
+    n = 12
+    g = _gradient_field(n)
+    c = np.array([0.7, -0.2, 1.1])
+    u = g + c[:, None, None, None]
+    eg = np.mean(np.sum(g * g, axis=0))
+    want = np.sqrt(eg / (np.dot(c, c) + eg))
+    assert abs(orc.div_rel(inputs.half_spectrum(u), n) - want) <= 1e-14
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.4, 1.1, np.pi / 2])
+def test_div_rel_of_one_plane_wave_is_the_angle_cosine(orc, theta):
+    # u = v cos(k.x) with |v| = 1 at angle theta to k: the longitudinal part
+    # is (v.k/|k|) k/|k| cos(k.x), so div_rel = |cos theta|, for any k
+    n = 16
+    x, y, z = inputs.grid(n)
+    k = np.array([2.0, -1.0, 3.0])
+    kh = k / np.linalg.norm(k)
+    e = np.cross(kh, [1.0, 0.0, 0.0])
+    e /= np.linalg.norm(e)
+    v = np.cos(theta) * kh + np.sin(theta) * e
+    u = v[:, None, None, None] * np.cos(k[0] * x + k[1] * y + k[2] * z)[None]
+    assert abs(orc.div_rel(inputs.half_spectrum(u), n) - abs(np.cos(theta))) <= 1e-14
