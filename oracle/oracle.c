@@ -22,6 +22,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cplx;
 
@@ -516,4 +519,14 @@ void orc_rhs_sparse(const orc_params *p, int nin, const int *kin, const cplx *ui
         double rate = hyperviscous_rate(p, k[0], k[1], k[2]);
         for (int i = 0; i < 3; ++i) out[3 * o + i] = b[i] - rate * uk[i];
     }
+}
+
+/* Threads the oracle's parallel loops use (for reporting its timings). */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

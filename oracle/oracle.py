@@ -83,6 +83,7 @@ def lib():
             "orc_energy_spectrum": (None, [I, P, P, I]),
             "orc_div_rel": (D, [I, P]),
             "orc_rhs_sparse": (None, [pp, I, P, P, I, P, P]),
+            "orc_num_threads": (I, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -287,6 +288,11 @@ def wasserstein1_fields(ua: np.ndarray, ub: np.ndarray):
 def div_rel(uh: np.ndarray, n: int) -> float:
     full = full_from_r2c(uh, n)
     return float(lib().orc_div_rel(n, _ptr(full)))
+
+
+def num_threads() -> int:
+    """Threads of the oracle's OpenMP loops."""
+    return int(lib().orc_num_threads())
 
 
 def kcut(n: int) -> int:
