@@ -223,6 +223,36 @@ ns_status ns_structure_functions(ns_ctx* ctx, const void* const* uhat, int32_t l
 ns_status ns_wasserstein1(ns_ctx* ctx, const void* a, int32_t na, const void* b, int32_t nb, int32_t n,
                           double* w_dev, double* mean_dev);
 
+/* Allocation-free right-hand side, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the result of ns_rhs for one sample, without a context.
+ *   params     as for ns_init with nsamples = 1 and n[0] the sample's size;
+ *              dtype, eps, s, m_cut, q_kind, theta and NS_PAD are honoured,
+ *              the other flags are ignored.  The passes use the built-in
+ *              schedules (those of a context made with NS_NO_TUNE), so the
+ *              output equals that context's ns_rhs bit for bit.
+ *   uhat_in    device array, one spectrum in the R2C layout (as ns_rhs)
+ *   rhs_out    device array of the same shape; may not alias uhat_in
+ *   hip_stream hipStream_t (NULL = the default stream)
+ * Workspaces: the compact states, the pass workspaces and the twiddle and
+ * damping tables live in one static device array of
+ * NS_NOALLOC_SCRATCH_BYTES per GPU, held from the first call on that GPU
+ * until the process ends.  A grid N (3n/2 with NS_PAD) needs, with
+ * K = floor((N-1)/3), M = 2K+1, Mx = K+1 and c the bytes of a complex number,
+ * about c (6 M^2 Mx + 6 N M Mx + 9 N^2 Mx + N) bytes: N <= 96 in FP32 and
+ * N <= 80 in FP64 fit.  Larger sizes give NS_ERR_ARG with nothing enqueued.
+ * The call allocates nothing: no hipMalloc, hipFree or allocating library
+ * routine.  When the table parameters (size, precision, eps, s, m_cut,
+ * q_kind, theta) differ from the previous call's on that GPU, it uploads the
+ * tables and synchronises the stream; otherwise it only enqueues kernels.
+ * Every call on one GPU shares that GPU's array and leaves its contents for
+ * the next: calls that overlap in time on one GPU (from several host threads
+ * or on several streams) race and give undefined results.
+ * Errors: NS_ERR_ARG / NS_ERR_UNSUPPORTED / NS_ERR_HIP; the message is
+ * returned by ns_last_error(NULL) on the calling thread. */
+#define NS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+ns_status ns_rhs_noalloc(const ns_params* params, const void* uhat_in, void* rhs_out, void* hip_stream);
+
 /* Synchronise the context's stream (convenience for callers without HIP). */
 ns_status ns_sync(ns_ctx* ctx);
 

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -785,6 +786,107 @@ ns_status ensure_graph(ns_ctx* c)
     return NS_OK;
 }
 
+
+// ---------------------------------------------------------------- allocation-free right-hand side
+// Workspaces of ns_rhs_noalloc: one static array per GPU.  Host code uses the
+// device address that hipGetSymbolAddress returns for the current device
+// (scratch_ptr), never the array's own name.
+static __device__ __align__(256) unsigned char scratch[NS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+
+struct ScratchState {
+    void* ptr = nullptr;  // device address of scratch on this GPU
+    // parameters of the tables the array holds (valid = uploaded)
+    bool valid = false, f64 = false;
+    int N = 0, L = 0, q_kind = 0;
+    double eps = 0, s = 0, m_cut = 0, theta = 0;
+};
+std::mutex g_scratch_mu;
+ScratchState g_scratch[kMaxDevices];
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Byte offsets of the regions of one sample's workspaces in the array.
+struct ScratchLayout {
+    size_t U0, U1, A, Bw, C, tw, rate, one, end;
+};
+
+ScratchLayout scratch_layout(const Group& g, size_t rsz)
+{
+    const size_t cw = 2 * rsz, N = g.N;
+    ScratchLayout l{};
+    size_t o = 0;
+    l.U0 = o;
+    o += align256(cw * g.st);
+    l.U1 = o;
+    o += align256(cw * g.st);
+    l.A = o;
+    o += align256(cw * 6 * N * g.MMx);
+    l.Bw = o;
+    o += align256(cw * 3 * N * N * g.Mx);
+    l.C = o;
+    o += align256(cw * 6 * N * N * g.Mx);
+    l.tw = o;
+    o += align256(cw * N);
+    l.rate = o;
+    o += align256(rsz * (3 * (size_t)g.K * g.K + 1));
+    l.one = o;
+    o += align256(sizeof(double));
+    l.end = o;
+    return l;
+}
+
+ns_status noalloc_fail(ns_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_init_error = buf;
+    return st;
+}
+
+#define NOALLOC_TRY(expr)                                                                                        \
+    do {                                                                                                         \
+        hipError_t e_ = (expr);                                                                                  \
+        if (e_ != hipSuccess) return noalloc_fail(NS_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// Uploads the twiddle and damping tables of g (and the unit time step) into
+// the array at base.  The host tables are stack buffers, so the upload waits
+// for the copies before it returns.
+template <typename R>
+ns_status noalloc_tables(const Group& g, const ns_params* p, char* base, const ScratchLayout& l, hipStream_t s)
+{
+    // every grid whose workspaces fit the array is far below these bounds
+    constexpr int kMaxN = 128, kMaxRate = 3 * 42 * 42 + 1;
+    if (g.N > kMaxN || 3 * g.K * g.K + 1 > kMaxRate) return noalloc_fail(NS_ERR_ARG, "N=%d is too large", g.N);
+    R tw[2 * kMaxN];
+    R rt[kMaxRate];
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int e = 0; e < g.N; ++e) {
+        const long double a = 2.0L * pi * (long double)e / (long double)g.N;
+        tw[2 * e] = (R)cosl(a);
+        tw[2 * e + 1] = (R)(-sinl(a));
+    }
+    const int nr = 3 * g.K * g.K + 1;
+    for (int k2 = 0; k2 < nr; ++k2) {
+        const double kabs = std::sqrt((double)k2);
+        double q;
+        if (kabs <= g.m_cut) q = 0.0;
+        else if (p->q_kind == 0) q = 1.0;
+        else q = 1.0 - std::pow(g.m_cut / kabs, (2.0 * p->s - 1.0) / p->theta);
+        rt[k2] = (R)(g.eps * std::pow((double)k2, p->s) * q);
+    }
+    NOALLOC_TRY(hipMemcpyAsync(base + l.tw, tw, sizeof(R) * 2 * g.N, hipMemcpyHostToDevice, s));
+    NOALLOC_TRY(hipMemcpyAsync(base + l.rate, rt, sizeof(R) * nr, hipMemcpyHostToDevice, s));
+    NOALLOC_TRY(launch_fill(reinterpret_cast<double*>(base + l.one), 1.0, 1, s));
+    NOALLOC_TRY(hipStreamSynchronize(s));
+    return NS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1306,6 +1408,87 @@ ns_status ns_energy_spectrum(ns_ctx* c, const void* const* uh, double* E, int32_
 ns_status ns_enstrophy_spectrum(ns_ctx* c, const void* const* uh, double* Z, int32_t kbins)
 {
     return spectrum_all(c, uh, Z, kbins, 1);
+}
+
+
+ns_status ns_rhs_noalloc(const ns_params* p, const void* uin, void* rout, void* hip_stream)
+{
+    if (!p) return noalloc_fail(NS_ERR_ARG, "params is null");
+    if (p->dtype != NS_F32 && p->dtype != NS_F64) return noalloc_fail(NS_ERR_ARG, "bad dtype %d", (int)p->dtype);
+    if (p->nsamples != 1 || !p->n) return noalloc_fail(NS_ERR_ARG, "ns_rhs_noalloc takes one sample (nsamples = 1)");
+    if (!uin || !rout) return noalloc_fail(NS_ERR_ARG, "uhat_in and rhs_out must be non-null");
+    if (uin == rout) return noalloc_fail(NS_ERR_ARG, "uhat_in and rhs_out may not alias");
+    if (!(p->s >= 0) || !std::isfinite(p->s)) return noalloc_fail(NS_ERR_ARG, "s must be finite and >= 0");
+    if (p->q_kind != 0 && p->q_kind != 1) return noalloc_fail(NS_ERR_ARG, "q_kind must be 0 or 1");
+    if (p->q_kind == 1 && !(p->theta > 0)) return noalloc_fail(NS_ERR_ARG, "theta must be > 0 for q_kind 1");
+    if (!std::isfinite(p->eps) || !std::isfinite(p->m_cut)) return noalloc_fail(NS_ERR_ARG, "eps and m_cut must be finite");
+    const bool f64 = p->dtype == NS_F64, pad = (p->flags & NS_PAD) != 0;
+    const int L = p->n[0];
+    if (pad && (L < 8 || L % 2 != 0)) return noalloc_fail(NS_ERR_UNSUPPORTED, "padded state of n=%d modes is not supported", L);
+    Group g;  // describes the sample; its buffers are regions of the array
+    g.L = L;
+    g.N = pad ? 3 * L / 2 : L;
+    g.kern = find_kernels(g.N, f64);
+    if (!g.kern) return noalloc_fail(NS_ERR_UNSUPPORTED, "grid size N=%d is not supported", g.N);
+    g.K = (g.N - 1) / 3;
+    g.M = 2 * g.K + 1;
+    g.Mx = g.K + 1;
+    g.MMx = (long long)g.M * g.Mx;
+    g.st = 3LL * g.M * g.MMx;
+    g.B = 1;
+    g.eps = p->eps >= 0 ? p->eps : 1e-3 * std::pow(32.0 / g.L, 2.0 * p->s - 1.0);
+    g.m_cut = p->m_cut >= 0 ? p->m_cut : g.L / 3.0;
+    const size_t rsz = f64 ? 8 : 4;
+    const ScratchLayout l = scratch_layout(g, rsz);
+    if (l.end > NS_NOALLOC_SCRATCH_BYTES)
+        return noalloc_fail(NS_ERR_ARG, "grid N=%d (%s) needs %zu bytes of scratch; the static array holds %zu", g.N,
+                            f64 ? "FP64" : "FP32", l.end, (size_t)NS_NOALLOC_SCRATCH_BYTES);
+    int dev = 0;
+    NOALLOC_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return noalloc_fail(NS_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    hipStream_t s = (hipStream_t)hip_stream;
+    char* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        ScratchState& ss = g_scratch[dev];
+        if (!ss.ptr) {
+            void* ptr = nullptr;
+            NOALLOC_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+            if (!ptr) return noalloc_fail(NS_ERR_HIP, "hipGetSymbolAddress returned a null address");
+            ss.ptr = ptr;
+        }
+        base = static_cast<char*>(ss.ptr);
+        const bool same = ss.valid && ss.f64 == f64 && ss.N == g.N && ss.L == g.L && ss.q_kind == p->q_kind &&
+                          ss.eps == g.eps && ss.s == p->s && ss.m_cut == g.m_cut && ss.theta == p->theta;
+        if (!same) {
+            ss.valid = false;
+            const ns_status st = f64 ? noalloc_tables<double>(g, p, base, l, s) : noalloc_tables<float>(g, p, base, l, s);
+            if (st) return st;
+            ss.valid = true;
+            ss.f64 = f64;
+            ss.N = g.N;
+            ss.L = g.L;
+            ss.q_kind = p->q_kind;
+            ss.eps = g.eps;
+            ss.s = p->s;
+            ss.m_cut = g.m_cut;
+            ss.theta = p->theta;
+        }
+    }
+    g.U0 = base + l.U0;
+    g.U1 = base + l.U1;
+    g.A = base + l.A;
+    g.Bw = base + l.Bw;
+    g.C = base + l.C;
+    g.tw = base + l.tw;
+    g.rate = base + l.rate;
+    g.ones = reinterpret_cast<double*>(base + l.one);
+    // the passes of ns_rhs with the built-in schedules (variant 0)
+    NOALLOC_TRY(launch_pack(f64, uin, g.U0, g.L, g.K, s));
+    const PassArgs a = pass_args(g, g.U0, g.U1, nullptr, 0.0, 0.0, 1.0, g.ones);
+    for (int pass = 0; pass < NS_NPASS; ++pass) NOALLOC_TRY(launch_pass(g, pass, 0, a, s));
+    NOALLOC_TRY(launch_unpack(f64, g.U1, rout, g.L, g.K, s));
+    return NS_OK;
 }
 
 }  // extern "C"

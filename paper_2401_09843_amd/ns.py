@@ -25,7 +25,7 @@ EXPORTS = ("ns_init", "ns_destroy", "ns_last_error", "ns_workspace_bytes", "ns_s
            "ns_inverse", "ns_project", "ns_rhs", "ns_step", "ns_tape_bytes", "ns_step_taped", "ns_adjoint_step", "ns_adjoint_steps",
            "ns_energy_spectrum", "ns_enstrophy_spectrum", "ns_moments", "ns_structure_functions",
            "ns_wasserstein1", "ns_sync", "ns_profile", "ns_profile_read",
-           "ns_variant_count", "ns_set_variant", "ns_tune_report")
+           "ns_variant_count", "ns_set_variant", "ns_tune_report", "ns_rhs_noalloc")
 NS_NPASS = 5
 PASS_NAMES = ("I1_inv_z", "I2_inv_y", "X_c2r_prod_r2c", "F2_fwd_y", "F3_fwd_z_epilogue")
 
@@ -81,6 +81,7 @@ def lib() -> ctypes.CDLL:
             "ns_variant_count": [P, I32, I32, ctypes.POINTER(I32)],
             "ns_set_variant": [P, I32, I32, I32],
             "ns_tune_report": [P, ctypes.c_char_p, S, ctypes.POINTER(S)],
+            "ns_rhs_noalloc": [ctypes.POINTER(_Params), P, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -363,6 +364,39 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def rhs_noalloc(uhat: torch.Tensor, out: torch.Tensor = None, eps=-1.0, s=1.5, m_cut=-1.0, q_kind=0, theta=1.0,
+                pad=False, stream=None) -> torch.Tensor:
+    """ns_rhs_noalloc: the right-hand side of one spectrum uhat [3, n, n, n//2+1]
+    (complex64 or complex128, contiguous, on the current device) without a
+    context; the library allocates nothing (its workspaces are a static
+    device array of NOALLOC_SCRATCH_BYTES per GPU).  Equals ns_rhs of a
+    Solver(n, tune=False, pad=pad) with the same parameters, bit for bit.
+    out: preallocated output of uhat's shape and dtype (else one is made
+    here, by torch)."""
+    if uhat.dtype not in (torch.complex64, torch.complex128) or not uhat.is_contiguous() or uhat.dim() != 4 \
+            or uhat.shape[0] != 3 or not (uhat.shape[1] == uhat.shape[2] == 2 * (uhat.shape[3] - 1)):
+        raise ValueError("uhat must be a contiguous complex tensor [3, n, n, n//2+1]")
+    if out is None:
+        out = torch.empty_like(uhat)
+    elif out.shape != uhat.shape or out.dtype != uhat.dtype or not out.is_contiguous() or out.device != uhat.device:
+        raise ValueError("out must be a contiguous tensor like uhat")
+    L = lib()
+    n = int(uhat.shape[1])
+    nn = (ctypes.c_int32 * 1)(n)
+    prm = _Params(NS_F32 if uhat.dtype == torch.complex64 else NS_F64, 1, nn, eps, s, m_cut, q_kind, theta,
+                  NS_PAD if pad else 0, None)
+    st = stream if stream is not None else torch.cuda.current_stream(uhat.device)
+    with torch.cuda.device(uhat.device):
+        code = L.ns_rhs_noalloc(ctypes.byref(prm), ctypes.c_void_p(uhat.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                ctypes.c_void_p(st.cuda_stream))
+    if code != NS_OK:
+        raise NSError(code, L.ns_last_error(None).decode())
+    return out
 
 
 class _Rollout(torch.autograd.Function):

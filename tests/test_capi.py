@@ -71,3 +71,23 @@ def test_calls_on_null_context_fail(ns):
     assert L.ns_rhs(None, None, None) == ns.NS_ERR_ARG
     assert L.ns_step(None, None, None, 1) == ns.NS_ERR_ARG
     assert L.ns_sync(None) == ns.NS_ERR_ARG
+
+
+def test_rhs_noalloc_rejects_bad_arguments(ns):
+    # every check below happens before the device is touched
+    L = ns.lib()
+    assert L.ns_rhs_noalloc(None, None, None, None) == ns.NS_ERR_ARG
+    p, keep = _params(ns, [32, 32])
+    assert L.ns_rhs_noalloc(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(32), None) == ns.NS_ERR_ARG
+    assert b"one sample" in L.ns_last_error(None)
+    p, keep = _params(ns, [32])
+    assert L.ns_rhs_noalloc(ctypes.byref(p), None, ctypes.c_void_p(32), None) == ns.NS_ERR_ARG
+    assert L.ns_rhs_noalloc(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), None) == ns.NS_ERR_ARG
+    assert b"alias" in L.ns_last_error(None)
+    p, keep = _params(ns, [33])
+    assert L.ns_rhs_noalloc(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(32), None) == ns.NS_ERR_UNSUPPORTED
+    # sizes whose workspaces exceed the static array: FP32 above 96, FP64 above 80
+    for n, dt in ((120, 0), (128, 0), (96, 1), (1024, 0)):
+        p, keep = _params(ns, [n], dtype=dt)
+        assert L.ns_rhs_noalloc(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(32), None) == ns.NS_ERR_ARG
+        assert b"scratch" in L.ns_last_error(None), n
