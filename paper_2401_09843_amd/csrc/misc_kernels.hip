@@ -2,6 +2,8 @@
 // (R2C) layout and the compact retained-mode layout, the in-place
 // truncation + Leray projection (eq. (2.5)), and the energy spectrum
 // (the energy-spectrum writer of Sec. 2.4).
+#include <cmath>
+
 #include "fft_engine.hpp"
 #include "misc_kernels.hpp"
 
@@ -435,7 +437,8 @@ template <typename R>
 static void sfun_dispatch(const R* u, int N, int lmax, int B, double p, double* part, hipStream_t s)
 {
     const dim3 grid(sfun_blocks(N), lmax, B);
-    const int ip = (p == (double)(int)p && p >= 1 && p <= 6) ? (int)p : 0;
+    // the range is checked before the conversion, which is undefined for |p| beyond int
+    const int ip = (p >= 1 && p <= 6 && p == std::floor(p)) ? (int)p : 0;
     switch (ip) {
         case 1: hipLaunchKernelGGL((k_sfun<R, 1>), grid, dim3(256), 0, s, u, N, p, part); break;
         case 2: hipLaunchKernelGGL((k_sfun<R, 2>), grid, dim3(256), 0, s, u, N, p, part); break;

@@ -116,15 +116,19 @@ def test_wasserstein1_rejects_bad_arguments(ns):
 
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
 def test_structure_functions_match_oracle(ns, orc, dtype, tol):
-    sizes = [32, 24]
-    uhs = [orc.initial_state(inputs.shear_layer(n, seed=7 + n)[0]) for n in sizes]
+    # interleaved size groups with several samples each, so the batched
+    # launch covers sample offsets inside a group and the placement of each
+    # sample's row; integer orders 1..6 take the multiplication kernels,
+    # 3.5 the pow kernel
+    sizes = [32, 24, 32, 24, 32]
+    uhs = [orc.initial_state(inputs.shear_layer(n, seed=7 + i)[0]) for i, n in enumerate(sizes)]
     E = ns.Solver(sizes, dtype=dtype)
     xs = [dev(u, dtype) for u in uhs]
-    for p in (1.0, 2.0, 3.5):
+    for p in (1.0, 2.0, 3.0, 4.0, 6.0, 3.5):
         S = E.structure_functions(xs, 12, p).cpu().numpy()
         for i, n in enumerate(sizes):
             ref = orc.structure_functions(uhs[i], n, 12, p)
-            assert np.max(np.abs(S[i] - ref)) <= tol * ref.max(), (n, p)
+            assert np.max(np.abs(S[i] - ref)) <= tol * ref.max(), (i, n, p)
         assert np.array_equal(S, E.structure_functions(xs, 12, p).cpu().numpy())
     with pytest.raises(ns.NSError):
         E.structure_functions(xs, 13, 2.0)  # beyond N/2 of the 24^3 sample
