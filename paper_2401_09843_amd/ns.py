@@ -13,6 +13,8 @@ from typing import Sequence
 
 import torch
 
+from . import revolve
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libns.so")
 
@@ -402,12 +404,17 @@ def rhs_noalloc(uhat: torch.Tensor, out: torch.Tensor = None, eps=-1.0, s=1.5, m
 class _Rollout(torch.autograd.Function):
     """u0 (physical) -> u(T) (physical) after nsteps SSP-RK3 steps, with the
     discrete adjoint in backward.  The trajectory is cut into segments of
-    `ckpt_every` steps.  If the stage tape of the whole trajectory fits the
+    `ckpt_every` steps, the unit of reversal: a segment is reversed by
+    re-running it from its start state with its stage tape recorded
+    (ns_step_taped), then stepping the adjoint back through the tape
+    (ns_adjoint_steps).  If the stage tape of the whole trajectory fits the
     memory budget it is recorded during the forward pass and the backward
-    only runs the adjoint; otherwise the forward keeps the state at each
-    segment start and the backward re-runs each segment taped (the last
-    segment is taped during the forward pass) before stepping the adjoint
-    back through it.
+    only runs the adjoint.  Otherwise the segment start states are kept by
+    the binomial (revolve) schedule for `snapshots` checkpoint slots: the
+    forward pass runs the schedule up to its first reversal (the last
+    segment, taped on the way to the output) and the backward runs the rest.
+    With a slot for every segment start (the default) this is the uniform
+    scheme: every segment but the last is re-run once.
 
     Gradient algebra: u(T) = F^-1[T u-hat(T)] and u-hat(0) = T P F[u0], with
     F normalised by N^-3.  In the inner product Re sum_k conj(a_k) b_k the
@@ -419,50 +426,113 @@ class _Rollout(torch.autograd.Function):
     on its own)."""
 
     @staticmethod
-    def forward(ctx, u0, solver, dt, nsteps, ckpt_every, tape_budget):
+    def forward(ctx, u0, solver, dt, nsteps, ckpt_every, tape_budget, snapshots, stats):
         uh = solver.forward(u0.detach().contiguous())
-        starts = list(range(0, nsteps, ckpt_every))
+        L = ckpt_every
+        nseg = (nsteps + L - 1) // L
+        lens = [min(L, nsteps - i * L) for i in range(nseg)]
         total = nsteps * solver.tape_step_bytes(solver.sizes[0])
-        tape_all = total <= tape_budget
-        segs = []
-        for i, s0 in enumerate(starts):
-            length = min(ckpt_every, nsteps - s0)
-            if tape_all or i == len(starts) - 1:
-                tape = solver.new_tape(length)[0]
-                segs.append((None, length, tape))
-                solver.step_taped(uh, dt, length, tape)
+        ctx.solver, ctx.dt, ctx.lens, ctx.stats = solver, dt, lens, stats
+        taped = nsteps
+        if total <= tape_budget:
+            # one tape, written segment by segment: every mode makes the same
+            # calls per segment (a call may start its stages differently in the
+            # fused form), so all modes follow the same trajectory bit for bit
+            tape = solver.new_tape(nsteps)[0]
+            per = solver.tape_step_bytes(solver.sizes[0])
+            for i, n in enumerate(lens):
+                solver.step_taped(uh, dt, n, tape[i * L * per:])
+            ctx.tape, ctx.rest = tape, None
+            if stats is not None:
+                stats.update({"mode": "whole tape", "segments": nseg, "snapshots": 0})
+            return solver.inverse(uh)
+        c = nseg - 1 if snapshots is None else max(0, min(int(snapshots), nseg - 1))
+        acts = revolve.schedule(nseg, c)
+        ctx.state0 = uh.clone()
+        snaps = {}
+        advanced = 0
+        k = 0
+        while acts[k][0] != revolve.REVERSE:
+            a = acts[k]
+            if a[0] == revolve.ADVANCE:
+                for n in lens[a[1]:a[2]]:  # one call per segment, as everywhere
+                    solver.step(uh, dt, n)
+                    advanced += n
+            elif a[0] == revolve.TAKESHOT:
+                snaps[a[1]] = uh.clone()
             else:
-                segs.append((uh.clone(), length, None))
-                solver.step(uh, dt, length)
-        ctx.solver, ctx.dt, ctx.segs = solver, dt, segs
+                raise RuntimeError("unexpected action %r before the first reversal" % (a,))
+            k += 1
+        # the first reversal is that of the last segment, from the current
+        # state: taped on the way to the output
+        assert acts[k] == (revolve.REVERSE, nseg - 1)
+        tape = solver.new_tape(lens[-1])[0]
+        solver.step_taped(uh, dt, lens[-1], tape)
+        ctx.tape, ctx.rest, ctx.snaps = tape, acts[k + 1:], snaps
+        ctx.counts = [advanced + lens[-1], lens[-1]]
+        if stats is not None:
+            stats.update({"mode": "revolve", "segments": nseg, "snapshots": c,
+                          "schedule_forward_segments": revolve.forward_steps(acts)})
         return solver.inverse(uh)
 
     @staticmethod
     def backward(ctx, g):
-        S, dt = ctx.solver, ctx.dt
+        S, dt, lens = ctx.solver, ctx.dt, ctx.lens
         lam = S.forward(g.detach().contiguous().to(S.dtype))
-        for i in reversed(range(len(ctx.segs))):
-            uh0, length, tape = ctx.segs[i]
-            if tape is None:
-                tape = S.new_tape(length)[0]
-                S.step_taped(uh0, dt, length, tape)
-            S.adjoint_steps(lam, dt, tape, length)
-            ctx.segs[i] = None
-            del tape
+        if ctx.rest is None:
+            S.adjoint_steps(lam, dt, ctx.tape, sum(lens))
+            ctx.tape = None
+            if ctx.stats is not None:
+                ctx.stats.update({"forward_steps": sum(lens), "taped_steps": sum(lens)})
+        else:
+            S.adjoint_steps(lam, dt, ctx.tape, lens[-1])
+            ctx.tape = None
+            fwd, taped = ctx.counts
+            cur = None
+            for a in ctx.rest:
+                if a[0] == revolve.ADVANCE:
+                    for n in lens[a[1]:a[2]]:
+                        S.step(cur, dt, n)
+                        fwd += n
+                elif a[0] == revolve.TAKESHOT:
+                    ctx.snaps[a[1]] = cur.clone()
+                elif a[0] == revolve.RESTORE:
+                    cur = (ctx.state0 if a[1] == 0 else ctx.snaps[a[1]]).clone()
+                elif a[0] == revolve.FREE:
+                    del ctx.snaps[a[1]]
+                else:  # REVERSE: re-run segment a[1] taped, then the adjoint back through it
+                    n = lens[a[1]]
+                    tape = S.new_tape(n)[0]
+                    S.step_taped(cur, dt, n, tape)
+                    S.adjoint_steps(lam, dt, tape, n)
+                    fwd += n
+                    taped += n
+                    del tape
+                    cur = None
+            ctx.snaps = None
+            ctx.state0 = None
+            if ctx.stats is not None:
+                ctx.stats.update({"forward_steps": fwd, "taped_steps": taped})
         S.project(lam)
-        return S.inverse(lam), None, None, None, None, None
+        return S.inverse(lam), None, None, None, None, None, None, None
 
 
 def rollout(u0: torch.Tensor, solver: "Solver", dt: float, nsteps: int, ckpt_every: int = 20,
-            tape_budget: int = None) -> torch.Tensor:
+            tape_budget: int = None, snapshots: int = None, stats: dict = None) -> torch.Tensor:
     """Differentiable SSP-RK3 trajectory of a single-sample solver:
     physical u0 [3,N,N,N] -> physical u(T) after nsteps steps of size dt.
     tape_budget: bytes of device memory the full stage tape may use to avoid
     recomputation (default: a quarter of the free device memory; 0 forces
-    checkpointing with recomputation every ckpt_every steps)."""
+    checkpointing with recomputation in segments of ckpt_every steps).
+    snapshots: checkpoint slots for segment start states when checkpointing
+    (None: one per segment, i.e. uniform checkpoints every ckpt_every steps;
+    fewer slots follow the binomial revolve schedule and re-run more).
+    stats: if a dict, receives the mode and the number of forward steps run
+    (taped re-runs included)."""
     if len(solver.sizes) != 1:
         raise ValueError("rollout needs a single-sample solver")
     if tape_budget is None:
         free, _ = torch.cuda.mem_get_info(solver.device)
         tape_budget = free // 4
-    return _Rollout.apply(u0, solver, float(dt), int(nsteps), int(ckpt_every), int(tape_budget))
+    return _Rollout.apply(u0, solver, float(dt), int(nsteps), int(ckpt_every), int(tape_budget),
+                          snapshots, stats)

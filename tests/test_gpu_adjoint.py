@@ -118,12 +118,11 @@ def test_rollout_gradient_matches_oracle(ns, orc):
 def test_rollout_gradient_finite_differences_128(ns):
     """128^3 FP64, 200 steps, checkpoints every 20: <grad, v> against
     central differences on 8 seeded directions.  At the configured step
-    eps = 1e-6 the second-order quotient carries roundoff of about
-    J * 1e-16 / eps, so there the error is measured against the scale
-    |grad| |v| of a directional derivative; a fourth-order stencil at
-    eps = 1e-5 (truncation and roundoff both near 1e-10 here) is compared
-    relative to the quotient itself.  Also reports the cost of forward +
-    backward over the plain forward."""
+    eps = 1e-6 the second-order quotient carries the evaluation noise of J
+    over eps (about 1e-6 of the derivative here), so the pin is a
+    fourth-order stencil at eps = 1e-5 (truncation and noise both near 1e-10
+    here), compared relative to the quotient itself.  Also checks the cost
+    of forward + backward over the plain forward."""
     n, steps = 128, 200
     u0, _, _ = inputs.shear_layer_torch(n, seed=0, device="cuda")
     dt = float(0.5 * (2 * np.pi / n) / u0.abs().sum(0).max().item())
@@ -161,24 +160,67 @@ def test_rollout_gradient_finite_differences_128(ns):
               % (mode, t_fwd, times[mode], times[mode] / t_fwd), flush=True)
     g = grads["checkpoints every 20 steps, segments recomputed"]
     assert torch.equal(g, grads["whole tape kept"])
+    # the adjoint's cost target holds with the whole tape kept (its 200
+    # steps of stage states take 9 GB here); the checkpointed form adds the
+    # re-run of 180 taped steps
+    assert times["whole tape kept"] / t_fwd <= 3.0
     rms = u0.pow(2).mean().sqrt()
-    gnorm = torch.linalg.vector_norm(g).item()
     worst_fine, worst_scaled = 0.0, 0.0
     for seed in range(2000, 2008):
         gen = torch.Generator(device="cuda").manual_seed(seed)
         v = torch.randn(u0.shape, generator=gen, device="cuda", dtype=torch.float64)
         v *= rms / v.pow(2).mean().sqrt()
         ad = torch.sum(g * v).item()
-        scale = gnorm * torch.linalg.vector_norm(v).item()
         fd6 = (forward_J(u0 + 1e-6 * v) - forward_J(u0 - 1e-6 * v)) / 2e-6
         # fourth-order central stencil at eps = 1e-5
         e = 1e-5
         fd4 = (8 * (forward_J(u0 + e * v) - forward_J(u0 - e * v))
                - (forward_J(u0 + 2 * e * v) - forward_J(u0 - 2 * e * v))) / (12 * e)
         r4 = abs(fd4 - ad) / abs(fd4)
-        r6 = abs(fd6 - ad) / scale
+        r6 = abs(fd6 - ad) / abs(fd6)
         worst_fine, worst_scaled = max(worst_fine, r4), max(worst_scaled, r6)
-        print("direction %d: adjoint %.12e fd4(1e-5) %.12e rel %.2e | fd(1e-6) %.12e rel %.2e err/(|g||v|) %.2e"
-              % (seed, ad, fd4, r4, fd6, abs(fd6 - ad) / abs(fd6), r6), flush=True)
+        print("direction %d: adjoint %.12e fd4(1e-5) %.12e rel %.2e | fd(1e-6) %.12e rel %.2e"
+              % (seed, ad, fd4, r4, fd6, r6), flush=True)
+    # The fourth-order stencil pins the gradient to 1e-6 relative per
+    # direction.  The second-order quotient at the configured eps = 1e-6
+    # carries the evaluation noise of J (the rounding of 200 steps, about
+    # |J1 - J0| between two equivalent runs) divided by eps, about 1e-6 of
+    # the derivative here, so it is held to 1e-5.
+    print("J evaluation noise between equivalent runs %.2e relative" % (abs(J1 - J0) / abs(J0)), flush=True)
     assert worst_fine <= 1e-6
-    assert worst_scaled <= 1e-6
+    assert worst_scaled <= 1e-5
+
+
+def test_rollout_revolve_schedules_match_the_whole_tape(ns):
+    """Checkpointing by the binomial schedule with fewer slots than segments
+    re-runs more steps but gives the same gradient bit for bit (every step's
+    stages and adjoint are computed by the same kernels); the forward steps
+    run match Griewank's count for the slots given."""
+    from paper_2401_09843_amd import revolve
+
+    n, steps, L = 64, 60, 5
+    u0, _, _ = inputs.shear_layer_torch(n, seed=3, device="cuda")
+    dt = float(0.5 * (2 * np.pi / n) / u0.abs().sum(0).max().item())
+    w = shell_weight(n, 4, 8)
+    S = ns.Solver(n, dtype=torch.float64)
+
+    def grad(budget, snapshots):
+        x = u0.clone().requires_grad_(True)
+        st = {}
+        J = shell_energy(ns.rollout(x, S, dt, steps, ckpt_every=L, tape_budget=budget, snapshots=snapshots,
+                                    stats=st), w)
+        J.backward()
+        return J.item(), x.grad, st
+
+    J0, g0, st0 = grad(None, None)
+    assert st0["mode"] == "whole tape" and st0["forward_steps"] == steps
+    nseg = steps // L
+    for snaps in (None, 5, 2, 1, 0):
+        J, g, st = grad(0, snaps)
+        c = nseg - 1 if snaps is None else snaps
+        want = L * revolve.binomial_forward_steps(nseg, c) + steps
+        print("snapshots %s: forward steps %d (binomial %d)" % (snaps, st["forward_steps"], want), flush=True)
+        assert st["mode"] == "revolve" and st["snapshots"] == c
+        assert st["forward_steps"] == want and st["taped_steps"] == steps
+        assert J == J0
+        assert torch.equal(g, g0)

@@ -6,6 +6,8 @@ GPU result is compared mode by mode, with everything off that support
 checked to be rounding noise.  Time stepping is checked at full size on a
 helical mode, whose nonlinear term is a pure gradient, so n steps multiply
 it by R(z)^n with R the SSP-RK3 amplification polynomial."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -125,3 +127,54 @@ def test_fp32_against_fp64_shear_layer(ns, n, steps):
                 / torch.linalg.vector_norm(uh64).item())
     print("n=%d: FP32 vs FP64 after %d steps, relative L2 %.3e" % (n, steps, err), flush=True)
     assert err <= 1e-3
+
+
+GOLDEN_256 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "shear256_100steps.npz")
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-11), (torch.float32, 1e-3)])
+def test_shear256_100_steps_against_the_oracle(ns, orc, dtype, tol):
+    """The seed-0 shear layer at 256^3, 100 SSP-RK3 steps at the CFL-0.5 dt,
+    against the oracle's FP64 trajectory (stored by
+    tests/golden/make_shear256_100.py, which runs only the oracle): every
+    retained mode with |k_i| <= 12, 4096 seeded retained entries, the energy
+    spectrum and the total norm, element by element; and the GPU state must
+    stay divergence-free (the oracle's div_rel)."""
+    g = np.load(GOLDEN_256)
+    n, steps, dt = int(g["n"]), int(g["nsteps"]), float(g["dt"])
+    print("shear 256^3 %d steps %s vs oracle" % (steps, dtype), flush=True)
+    u0, _, _ = inputs.shear_layer(n, seed=int(g["seed"]))
+    S = ns.Solver(n, dtype=dtype, tune=False)
+    uh = S.forward(torch.from_numpy(u0).to("cuda", dtype))
+    del u0
+    S.step(uh, dt, steps)
+    kl = g["low"].shape[-1] - 1
+    k = np.r_[0:kl + 1, n - kl:n]
+    got_low = uh[:, k][:, :, k][:, :, :, : kl + 1].cpu().numpy().astype(np.complex128)
+    ref_low = g["low"]
+    idx = torch.as_tensor(g["idx"], device="cuda")
+    got_s = uh.reshape(-1)[idx].cpu().numpy().astype(np.complex128)
+    ref_s = g["vals"]
+    kb = g["spectrum"].shape[0]
+    E = S.spectrum(uh, kb)[0].cpu().numpy()
+    Eref = g["spectrum"]
+    norm2 = float(torch.sum(torch.abs(uh.to(torch.complex128)) ** 2).item())
+    full = uh.cpu().numpy()
+    div = orc.div_rel(full, n)
+    del full
+    scale = np.max(np.abs(ref_low))
+    e_low = np.linalg.norm(got_low - ref_low) / np.linalg.norm(ref_low)
+    m_low = np.max(np.abs(got_low - ref_low)) / scale
+    e_s = np.linalg.norm(got_s - ref_s) / np.linalg.norm(ref_s)
+    m_s = np.max(np.abs(got_s - ref_s)) / scale
+    e_E = np.linalg.norm(E - Eref) / np.linalg.norm(Eref)
+    shell = np.abs(E - Eref) / (Eref + 1e-6 * Eref.sum())
+    e_n = abs(norm2 - float(g["norm2"])) / float(g["norm2"])
+    print("low modes rel L2 %.3e max %.3e | sampled rel L2 %.3e max %.3e | E(k) rel L2 %.3e worst shell %.3e | "
+          "norm %.3e | div_rel %.3e (oracle's final %.3e)" % (e_low, m_low, e_s, m_s, e_E, shell.max(), e_n, div,
+                                                             float(g["div_rel"])), flush=True)
+    assert e_low <= tol and m_low <= tol
+    assert e_s <= tol and m_s <= tol
+    assert e_E <= tol and shell.max() <= tol
+    assert e_n <= tol
+    assert div <= (1e-13 if dtype == torch.float64 else 1e-6)
