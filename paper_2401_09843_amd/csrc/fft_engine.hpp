@@ -295,17 +295,39 @@ __device__ __forceinline__ int lds_slot(int pos)
     }
 }
 
+// Synchronisation of an LDS exchange.  WS = false: the whole block.  WS =
+// true: only the calling wavefront, for lines whose threads all lie in one
+// wavefront; a wavefront's LDS operations are executed in program order, so
+// the fences only keep the compiler from moving LDS accesses across it.
+template <bool WS>
+__device__ __forceinline__ void lds_sync()
+{
+    if constexpr (WS) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // Stage s of a transform of length N held by G threads: compute the
 // butterflies, then (unless it is the last stage) exchange through LDS into
 // the register layout of the next stage.  lds points at this line's slot 0;
 // element pos lives at lds[lds_slot<PD, P, R, ES>(pos) * LS].  With SP = 1 the
 // exchange moves the real and then the imaginary parts through a real-valued
 // buffer of the same layout (half the LDS, twice the barriers).
-template <int N, int G, int DIR, int PD, int LS, int SP, typename T, int P, int OFF, int... Rs>
+// DB = true: the exchanges alternate between two LDS buffers, dbo bytes
+// apart, with par (kept by the caller across transforms) selecting the one
+// to write next.  Every thread then finishes reading an exchange's buffer
+// before it can pass the barrier of the following exchange, which writes
+// the other buffer, so the barrier after the reads is not needed.
+template <int N, int G, int DIR, int PD, int LS, int SP, bool WS, bool DB, typename T, int P, int OFF, int... Rs>
 struct Stages;
 
-template <int N, int G, int DIR, int PD, int LS, int SP, typename T, int P, int OFF, int R, int... Rest>
-struct Stages<N, G, DIR, PD, LS, SP, T, P, OFF, R, Rest...> {
+template <int N, int G, int DIR, int PD, int LS, int SP, bool WS, bool DB, typename T, int P, int OFF, int R,
+          int... Rest>
+struct Stages<N, G, DIR, PD, LS, SP, WS, DB, T, P, OFF, R, Rest...> {
     static constexpr int E = N / G;
     static constexpr int NB = N / (R * G);
     static_assert(NB * R * G == N, "G must divide N / R for every radix");
@@ -331,9 +353,12 @@ struct Stages<N, G, DIR, PD, LS, SP, T, P, OFF, R, Rest...> {
     }
 
     template <int R2, typename L, typename Get, typename Put>
-    __device__ __forceinline__ static void exchange(cpx<T> (&v)[E], int t, L* lds, Get get, Put put)
+    __device__ __forceinline__ static void exchange(cpx<T> (&v)[E], int t, L* lds0, Get get, Put put, int dbo,
+                                                    int& par)
     {
         constexpr int ES = sizeof(L);
+        L* lds = lds0;
+        if constexpr (DB) lds = reinterpret_cast<L*>(reinterpret_cast<char*>(lds0) + par * dbo);
         if constexpr (fast_write<ES>()) {
             const int k = t % P;
             L* base = lds + lds_slot<PD, P, R, ES>((t - k) * R + k) * LS;
@@ -351,7 +376,7 @@ struct Stages<N, G, DIR, PD, LS, SP, T, P, OFF, R, Rest...> {
                 for (int m = 0; m < R; ++m) lds[lds_slot<PD, P, R, ES>(j + m * P) * LS] = get(v[q * R + m]);
             }
         }
-        __syncthreads();
+        lds_sync<WS>();
         if constexpr (fast_read<R2, ES>()) {
             const L* base = lds + lds_slot<PD, P, R, ES>(t) * LS;
 #pragma unroll
@@ -366,11 +391,13 @@ struct Stages<N, G, DIR, PD, LS, SP, T, P, OFF, R, Rest...> {
                 for (int m = 0; m < R2; ++m)
                     put(v[q * R2 + m], lds[lds_slot<PD, P, R, ES>(t + q * G + m * (N / R2)) * LS]);
         }
-        __syncthreads();
+        if constexpr (DB) par ^= 1;
+        else lds_sync<WS>();
     }
 
     template <typename L>
-    __device__ __forceinline__ static void run(cpx<T> (&v)[E], int t, L* lds, const cpx<T>* __restrict__ tw)
+    __device__ __forceinline__ static void run(cpx<T> (&v)[E], int t, L* lds, const cpx<T>* __restrict__ tw, int dbo,
+                                               int& par)
     {
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
@@ -385,13 +412,14 @@ struct Stages<N, G, DIR, PD, LS, SP, T, P, OFF, R, Rest...> {
         if constexpr (sizeof...(Rest) > 0) {
             constexpr int R2 = Radices<Rest...>::first;
             if constexpr (SP == 0) {
-                exchange<R2>(v, t, lds, [](cpx<T> a) { return a; }, [](cpx<T>& d, cpx<T> a) { d = a; });
+                exchange<R2>(v, t, lds, [](cpx<T> a) { return a; }, [](cpx<T>& d, cpx<T> a) { d = a; }, dbo, par);
             } else {
                 T* l = reinterpret_cast<T*>(lds);
-                exchange<R2>(v, t, l, [](cpx<T> a) { return a.x; }, [](cpx<T>& d, T a) { d.x = a; });
-                exchange<R2>(v, t, l, [](cpx<T> a) { return a.y; }, [](cpx<T>& d, T a) { d.y = a; });
+                exchange<R2>(v, t, l, [](cpx<T> a) { return a.x; }, [](cpx<T>& d, T a) { d.x = a; }, dbo, par);
+                exchange<R2>(v, t, l, [](cpx<T> a) { return a.y; }, [](cpx<T>& d, T a) { d.y = a; }, dbo, par);
             }
-            Stages<N, G, DIR, PD, LS, SP, T, P * R, OFF + (P > 1 ? (R - 1) * P : 0), Rest...>::run(v, t, lds, tw);
+            Stages<N, G, DIR, PD, LS, SP, WS, DB, T, P * R, OFF + (P > 1 ? (R - 1) * P : 0), Rest...>::run(v, t, lds, tw,
+                                                                                                      dbo, par);
         }
     }
 };
@@ -450,6 +478,13 @@ struct Plan<N_, G_, Radices<Rs...>> {
     {
         for (int i = threadIdx.x; i < tw_len; i += blockDim.x) TwTable<N_, 1, Rs...>::fill(i, dst, src);
     }
+    // the same from the table of a length STRIDE * N (every STRIDE-th entry)
+    template <int STRIDE, typename T>
+    __device__ __forceinline__ static void fill_tw_from(cpx<T>* dst, const cpx<T>* __restrict__ src)
+    {
+        for (int i = threadIdx.x; i < tw_len; i += blockDim.x)
+            dst[i] = src[STRIDE * TwTable<N_, 1, Rs...>::src_index(i)];
+    }
     template <typename T>
     __device__ __forceinline__ static void load_tw(cpx<T>* dst, const cpx<T>* __restrict__ src)
     {
@@ -502,13 +537,27 @@ struct Plan<N_, G_, Radices<Rs...>> {
         return ext;
     }
 
-    // ST = true selects the per-stage padding (for LS = 1)
-    template <int DIR, int LS, int SP = 0, bool ST = false, typename T>
+    // ST = true selects the per-stage padding (for LS = 1); WS = true
+    // synchronises the exchanges per wavefront (the G threads of a line must
+    // lie in one wavefront)
+    template <int DIR, int LS, int SP = 0, bool ST = false, bool WS = false, typename T>
     __device__ __forceinline__ static void run(cpx<T> (&v)[E], int t, cpx<T>* lds, const cpx<T>* __restrict__ tw)
     {
         static_assert(!ST || (LS == 1 && SP == 0), "per-stage padding is laid out for one line at unit stride");
-        Stages<N_, G_, DIR, ST ? 0 : R0, LS, SP, T, 1, 0, Rs...>::run(v, t, lds, tw);
+        static_assert(!WS || (G_ <= 64 && 64 % G_ == 0), "wavefront-synchronous exchanges need lines inside a wavefront");
+        int par = 0;
+        Stages<N_, G_, DIR, ST ? 0 : R0, LS, SP, WS, false, T, 1, 0, Rs...>::run(v, t, lds, tw, 0, par);
     }
+    // the same with double-buffered exchanges (the second buffer dbo bytes
+    // after the first; par selects the next buffer to write and is updated)
+    template <int DIR, int LS, int SP = 0, typename T>
+    __device__ __forceinline__ static void run_db(cpx<T> (&v)[E], int t, cpx<T>* lds, const cpx<T>* __restrict__ tw,
+                                                  int dbo, int& par)
+    {
+        Stages<N_, G_, DIR, R0, LS, SP, false, true, T, 1, 0, Rs...>::run(v, t, lds, tw, dbo, par);
+    }
+    // exchanges per transform (each split exchange counts twice)
+    static constexpr int exchanges(int sp) { return (int)(sizeof...(Rs) - 1) * (sp ? 2 : 1); }
     // position of register element i = q * R + m at stage-0 input / final output
     __device__ __forceinline__ static constexpr int in_pos(int t, int i) { return t + (i / R0) * G + (i % R0) * (N / R0); }
     __device__ __forceinline__ static constexpr int out_pos(int t, int i) { return t + (i / RL) * G + (i % RL) * (N / RL); }

@@ -41,6 +41,17 @@ struct Cut {
     static constexpr int K = (N - 1) / 3, M = 2 * K + 1;
 };
 
+// Slot i of a thread's final output (row out_pos(t, i), t < G) holds a
+// retained row |k_z| <= K for some thread t; slots that never do need no
+// epilogue code.
+template <class P>
+__device__ __forceinline__ constexpr bool slot_may_keep(int i)
+{
+    constexpr int N = P::N, K = Cut<P::N>::K;
+    const int base = (i / P::RL) * P::G + (i % P::RL) * (N / P::RL);
+    return base <= K || base + P::G - 1 >= N - K;
+}
+
 // ------------------------------------------------------------------ I1/I2/F2
 // LDS bytes of a column tile (complex or split exchange), 16-byte aligned
 template <class P, int T, int SP, typename R>
@@ -49,13 +60,15 @@ constexpr size_t tile_bytes()
     return ((SP ? sizeof(R) : sizeof(cpx<R>)) * P::lds_len * T + 15) / 16 * 16;
 }
 
-template <class P, int T, int DIR, int MODE, int SP, int W, typename R>
+// DB = 1 double-buffers the LDS exchanges (one barrier per exchange).
+template <class P, int T, int DIR, int MODE, int SP, int W, typename R, int DB = 0>
 __global__ void __launch_bounds__(P::G* T, W) k_colfft(ColArgs a)
 {
     constexpr int N = P::N, E = P::E, KC = Cut<N>::K, MC = Cut<N>::M;
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int TB = (int)tile_bytes<P, T, SP, R>();
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
-    cpx<R>* twl = reinterpret_cast<cpx<R>*>(smem_raw + tile_bytes<P, T, SP, R>());
+    cpx<R>* twl = reinterpret_cast<cpx<R>*>(smem_raw + (DB ? 2 : 1) * TB);
     const int tid = threadIdx.x, c = tid % T, g = tid / T;
     const long long q = xcd_tile(gridDim.x) * T + c;
     const bool valid = q < a.Q;
@@ -76,8 +89,12 @@ __global__ void __launch_bounds__(P::G* T, W) k_colfft(ColArgs a)
         v[i] = (valid && r >= 0) ? in[r * a.S] : cpx<R>{0, 0};
     }
     P::template load_tw<R>(twl, static_cast<const cpx<R>*>(a.tw));
-    if constexpr (SP) P::template run<DIR, T, 1>(v, g, reinterpret_cast<cpx<R>*>(reinterpret_cast<R*>(lds) + c), twl);
-    else P::template run<DIR, T, 0>(v, g, lds + c, twl);
+    {
+        cpx<R>* base = SP ? reinterpret_cast<cpx<R>*>(reinterpret_cast<R*>(lds) + c) : lds + c;
+        int par = 0;
+        if constexpr (DB) P::template run_db<DIR, T, SP>(v, g, base, twl, TB, par);
+        else P::template run<DIR, T, SP>(v, g, base, twl);
+    }
 #pragma unroll
     for (int i = 0; i < E; ++i) {
         const int n = P::out_pos(g, i);
@@ -171,7 +188,9 @@ constexpr int x_line_len()
 // B_k = (Z_k - conj Z_{N-k})/(2i).
 // BPC > 0 (product pass only): persistent blocks, BPC per compute unit,
 // that build the twiddle tables once and then walk the tiles of U units.
-template <class PI, class PF, int U, int MODE, int W, typename R, int BPC = 0>
+// WS = true: the exchanges of a line synchronise its wavefront only (lines
+// of at most 64 threads lie inside one wavefront).
+template <class PI, class PF, int U, int MODE, int W, typename R, int BPC = 0, bool WS = false>
 __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
 {
     constexpr int N = PI::N, G = PI::G, E = PI::E;
@@ -195,7 +214,7 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
     cpx<R> ti[PI::template tw_per_thread<NT> > 0 ? PI::template tw_per_thread<NT> : 1];
     cpx<R> tf[PF::template tw_per_thread<NT> > 0 ? PF::template tw_per_thread<NT> : 1];
     // (FP32 only: the FP64 build keeps the staged entries in scratch memory)
-    constexpr bool STAGE = MODE == X_RHS && BPC == 0 && sizeof(R) == 4;
+    constexpr bool STAGE = MODE == X_RHS && BPC == 0 && sizeof(R) == 4 && !WS;
     if constexpr (STAGE) {
         PI::template fetch_tw<NT>(ti, static_cast<const cpx<R>*>(a.tw));
         if constexpr (!SAME) PF::template fetch_tw<NT>(tf, static_cast<const cpx<R>*>(a.tw));
@@ -244,15 +263,15 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
         load_raw(c, v);
         int t = t0;
         asm volatile("" : "+v"(t));
-        PI::template run<+1, 1, 0, true>(v, t, my, twI);
+        PI::template run<+1, 1, 0, true, WS>(v, t, my, twI);
     };
 
     // forward (R2C) of v = a + i b; store k_x <= K of both lines as product p
     auto fwd_store = [&](int p, cpx<R>(&v)[E]) {
-        PF::template run<-1, 1, 0, true>(v, t, my, twF);
+        PF::template run<-1, 1, 0, true, WS>(v, t, my, twF);
 #pragma unroll
         for (int i = 0; i < E; ++i) my[PF::out_pos(t, i)] = v[i];
-        __syncthreads();
+        lds_sync<WS>();
         const R h = (R)(0.5 * a.scale);
         cpx<R>* o1 = static_cast<cpx<R>*>(a.out) + samp * a.out_ss + p * a.out_cs + l1 * Mx;
         cpx<R>* o2 = o1 + Mx;
@@ -264,7 +283,7 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
                 o2[kx] = {(zk.y + zm.y) * h, (zm.x - zk.x) * h};
             }
         }
-        __syncthreads();
+        lds_sync<WS>();
     };
 
     if constexpr (MODE == X_RHS) {
@@ -279,9 +298,9 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
             if constexpr (!SAME) PF::template put_tw<NT>(twF, tf);
             __syncthreads();
         }
-        PI::template run<+1, 1, 0, true>(z0, t, my, twI);
-        PI::template run<+1, 1, 0, true>(z1, t, my, twI);
-        PI::template run<+1, 1, 0, true>(z2, t, my, twI);
+        PI::template run<+1, 1, 0, true, WS>(z0, t, my, twI);
+        PI::template run<+1, 1, 0, true, WS>(z1, t, my, twI);
+        PI::template run<+1, 1, 0, true, WS>(z2, t, my, twI);
         // B_ij = u_i u_j, upper triangle (xx, xy, xz, yy, yz, zz); real parts
         // belong to line l1, imaginary parts to line l2
 #pragma unroll
@@ -371,12 +390,123 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
     }
 }
 
+// ------------------------------------------------------------------ X pass, half-length form
+// Each real x-line of length N is transformed by a complex transform of
+// length H = N/2 held by G <= 64 threads of one wavefront (the line's
+// exchanges need no block barrier).  The C2R packs even and odd samples, z_m = x_{2m} + i x_{2m+1}:
+// splitting x_n = sum_k X_k exp(2 pi i k n / N) by the parity of n and
+// folding k + H onto k gives z = IDFT_H(Z) with
+//   Z_k = (X_k + conj X_{H-k}) + i W^{-k} (X_k - conj X_{H-k}),  W = exp(-2 pi i / N),
+// for k < H (X_{H-k} = 0 above the cutoff; the Nyquist mode X_H is truncated).
+// The R2C of a real product line y unpacks Z = DFT_H(y_{2m} + i y_{2m+1}):
+//   Y_k = (Z_k + conj Z_{H-k}) / 2 - (i / 2) W^k (Z_k - conj Z_{H-k}),  Z_H = Z_0,
+// which are the even-sample and odd-sample transforms recombined.  A lane
+// holds the same positions k = t + G i at the input and the output of the
+// plan, so one register set of W^k serves both.
+template <class PH, int U, int W, typename R>
+__global__ void __launch_bounds__(PH::G* U, W) k_xhalf(XArgs a)
+{
+    constexpr int H = PH::N, N = 2 * H, G = PH::G, E = PH::E;
+    static_assert(G <= 64 && 64 % G == 0, "lines inside one wavefront");
+    static_assert(PH::R0 == PH::RL, "the forward transform takes the inverse's output order");
+    static_assert(PH::R0 == E, "a lane's positions are t + G i, i < E");
+    constexpr int K = (N - 1) / 3, Mx = K + 1;
+    static_assert(K < H, "the cutoff lies below the Nyquist mode");
+    constexpr int LL = PH::template lds_len_st<sizeof(cpx<R>)>();
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<R>* twl = reinterpret_cast<cpx<R>*>(smem_raw) + U * LL;
+    PH::template fill_tw_from<2, R>(twl, static_cast<const cpx<R>*>(a.tw));
+    const int tid = threadIdx.x, u = tid / G, t = tid % G;
+    cpx<R>* my = reinterpret_cast<cpx<R>*>(smem_raw) + u * LL;
+    const long long line = xcd_tile(gridDim.x) * U + u;
+    const bool valid = line < 2 * a.nunits;
+    const long long L = valid ? line : 0;
+    const long long samp = L / ((long long)N * N), l1 = L % ((long long)N * N);
+    const cpx<R>* __restrict__ tw = static_cast<const cpx<R>*>(a.tw);
+    static_assert(PH::in_pos(1, 1) == PH::out_pos(1, 1), "input and output positions coincide");
+    cpx<R> wk[E];  // W^k at this lane's positions
+#pragma unroll
+    for (int i = 0; i < E; ++i) wk[i] = tw[PH::in_pos(t, i)];
+    __syncthreads();  // stage tables
+
+    // Z of component c of this line, from its half spectrum
+    auto load_z = [&](int c, cpx<R>(&z)[E]) {
+        const cpx<R>* __restrict__ p = static_cast<const cpx<R>*>(a.in) + samp * a.in_ss + c * a.in_cs + l1 * Mx;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int k = PH::in_pos(t, i);
+            cpx<R> A = {0, 0}, Bc = {0, 0};  // X_k and conj X_{H-k}
+            if (valid) {
+                if (k <= K) {
+                    A = p[k];
+                    if (k == 0) A.y = 0;  // the Hermitian part of the k = 0 mode
+                }
+                if (H - k <= K) {
+                    const cpx<R> b = p[H - k];
+                    Bc = {b.x, -b.y};
+                }
+            }
+            const cpx<R> sm = {A.x + Bc.x, A.y + Bc.y}, d = {A.x - Bc.x, A.y - Bc.y};
+            const cpx<R> e = {wk[i].x * d.x + wk[i].y * d.y, wk[i].x * d.y - wk[i].y * d.x};  // W^{-k} d
+            z[i] = {sm.x - e.y, sm.y + e.x};
+        }
+    };
+    // forward transform of the packed product v, then Y_k, k <= K, of product p
+    auto fwd_store = [&](int p, cpx<R>(&v)[E]) {
+        PH::template run<-1, 1, 0, true, true>(v, t, my, twl);
+#pragma unroll
+        for (int i = 0; i < E; ++i) my[PH::out_pos(t, i)] = v[i];
+        lds_sync<true>();
+        const R h = (R)(0.5 * a.scale);
+        cpx<R>* o = static_cast<cpx<R>*>(a.out) + samp * a.out_ss + p * a.out_cs + l1 * Mx;
+#pragma unroll
+        for (int j = 0; j * G <= K; ++j) {
+            const int k = t + j * G;
+            if (k <= K) {
+                const cpx<R> zk = my[k], zm = my[(H - k) % H];
+                const cpx<R> sm = {zk.x + zm.x, zk.y - zm.y}, d = {zk.x - zm.x, zk.y + zm.y};
+                const cpx<R> f = {wk[j].x * d.x - wk[j].y * d.y, wk[j].x * d.y + wk[j].y * d.x};  // W^k d
+                if (valid) o[k] = {(sm.x + f.y) * h, (sm.y - f.x) * h};
+            }
+        }
+        lds_sync<true>();
+    };
+    static_assert(K < E * G, "the lane's W^k set covers the stored modes");
+
+    cpx<R> z0[E], z1[E], z2[E], v[E];
+    load_z(0, z0);
+    load_z(1, z1);
+    load_z(2, z2);
+    PH::template run<+1, 1, 0, true, true>(z0, t, my, twl);
+    PH::template run<+1, 1, 0, true, true>(z1, t, my, twl);
+    PH::template run<+1, 1, 0, true, true>(z2, t, my, twl);
+    // B_ij = u_i u_j (xx, xy, xz, yy, yz, zz): real parts are the even
+    // samples, imaginary parts the odd ones
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        auto mul = [&](const cpx<R>(&za)[E], const cpx<R>(&zb)[E]) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) v[i] = {za[i].x * zb[i].x, za[i].y * zb[i].y};
+        };
+        switch (p) {
+            case 0: mul(z0, z0); break;
+            case 1: mul(z0, z1); break;
+            case 2: mul(z0, z2); break;
+            case 3: mul(z1, z1); break;
+            case 4: mul(z1, z2); break;
+            default: mul(z2, z2); break;
+        }
+        fwd_store(p, v);
+    }
+}
+
 // ------------------------------------------------------------------ F3 pass
 // PRE = 1 issues the loads of component p + 1 before the transform of p.
 // ZI = 1 (F3_RHS only) also transforms the new state back along z, zero-
 // padded to N rows, and writes it to a.zinv: the inverse z pass of the next
 // stage's right-hand side, done while the state is still in registers.
-template <class P, int T, int MODE, int SP, int W, typename R, int PRE = 0, int ZI = 0>
+// DB = 1 double-buffers the LDS exchanges (one barrier per exchange).
+template <class P, int T, int MODE, int SP, int W, typename R, int PRE = 0, int ZI = 0, int DB = 0>
 __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
 {
     constexpr int N = P::N, E = P::E;
@@ -384,25 +514,48 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
     static_assert(ZI == 0 || MODE == F3_RHS, "the fused inverse follows the stage epilogue");
     static_assert(P::slot_map_ok(), "output and input slots of a thread cover the same rows");
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int TB = (int)tile_bytes<P, T, SP, R>();
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
-    cpx<R>* twl = reinterpret_cast<cpx<R>*>(smem_raw + tile_bytes<P, T, SP, R>());
+    cpx<R>* twl = reinterpret_cast<cpx<R>*>(smem_raw + (DB ? 2 : 1) * TB);
     P::template load_tw<R>(twl, static_cast<const cpx<R>*>(a.tw));
+    int par = 0;  // next exchange buffer (DB)
+    // transform of v in direction D by the tile's LDS (column cc)
+    auto fft = [&](auto dir, cpx<R>(&v)[E], int gg, int cc) {
+        constexpr int D = decltype(dir)::value;
+        cpx<R>* base = SP ? reinterpret_cast<cpx<R>*>(reinterpret_cast<R*>(lds) + cc) : lds + cc;
+        if constexpr (DB) P::template run_db<D, T, SP>(v, gg, base, twl, TB, par);
+        else P::template run<D, T, SP>(v, gg, base, twl);
+    };
     const int tid = threadIdx.x, c = tid % T, g = tid / T;
     constexpr int K = Cut<N>::K, M = Cut<N>::M, Mx = K + 1;
-    const long long q = xcd_tile(gridDim.x) * T + c;
-    const bool valid = q < a.Q;
-    const long long samp = valid ? q / a.MMx : 0;
-    const int s = valid ? (int)(q % a.MMx) : 0;
-    auto load = [&](int p, cpx<R>(&v)[E], int gg) {
-        const cpx<R>* __restrict__ in = static_cast<const cpx<R>*>(a.in) + samp * a.in_ss + s;
+    // column of this thread in tile `tile`
+    struct Col {
+        bool valid;
+        long long samp;
+        int s;
+    };
+    auto column = [&](long long tile) {
+        const long long q = tile * T + c;
+        Col k;
+        k.valid = q < a.Q;
+        k.samp = k.valid ? q / a.MMx : 0;
+        k.s = k.valid ? (int)(q % a.MMx) : 0;
+        return k;
+    };
+    auto load = [&](int p, cpx<R>(&v)[E], int gg, const Col& k) {
+        const cpx<R>* __restrict__ in = static_cast<const cpx<R>*>(a.in) + k.samp * a.in_ss + k.s;
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int n = P::in_pos(gg, i);
-            v[i] = valid ? in[p * a.in_cs + (long long)n * a.MMx] : cpx<R>{0, 0};
+            v[i] = k.valid ? in[p * a.in_cs + (long long)n * a.MMx] : cpx<R>{0, 0};
         }
     };
     cpx<R> nxt[PRE ? E : 1];
-    if constexpr (PRE) load(0, nxt, g);
+    // the tile: the component loop, then the epilogue (and the fused inverse)
+    auto tile_body = [&](const Col& col) {
+    const bool valid = col.valid;
+    const long long samp = col.samp;
+    const int s = col.s;
     const int jy = s / Mx, kxi = s % Mx;
     const int kyi = jy <= K ? jy : jy - M;
     const R kx = (R)kxi, ky = (R)kyi;
@@ -427,12 +580,11 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
         if constexpr (PRE) {
 #pragma unroll
             for (int i = 0; i < E; ++i) v[i] = nxt[i];
-            if (p + 1 < NC) load(p + 1, nxt, gg);
+            if (p + 1 < NC) load(p + 1, nxt, gg, col);
         } else {
-            load(p, v, gg);
+            load(p, v, gg, col);
         }
-        if constexpr (SP) P::template run<-1, T, 1>(v, gg, reinterpret_cast<cpx<R>*>(reinterpret_cast<R*>(lds) + cc), twl);
-        else P::template run<-1, T, 0>(v, gg, lds + cc, twl);
+        fft(std::integral_constant<int, -1>{}, v, gg, cc);
         if constexpr (MODE == F3_RHS) {
             // component p = (i, j) of the upper triangle adds k_j B to b_i
             // and, off the diagonal, k_i B to b_j: b_r += (wxy_r + wz_r k_z) B
@@ -473,56 +625,29 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
     const R sc = (R)a.scale;
     const double dts = (MODE != F3_PROJ && valid) ? a.dt[samp] : 0.0;
     const R* __restrict__ rate = static_cast<const R*>(a.rate);
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
+
+    // Epilogue.  The state reads of a group of output slots are all issued
+    // before any of the group's arithmetic and stores, so their latencies
+    // overlap (the output may alias a state that is read, so loads cannot be
+    // moved across earlier stores).  Slots that hold a truncated row for
+    // every thread are skipped at compile time.
+    // row kz of slot i and its compact index (-1: truncated)
+    auto row = [&](int i, int& kzi, int& jz) {
         const int n = P::out_pos(g, i);
-        const int jz = compact_of(n, N, K, M);
-        if (!valid || jz < 0) {
-            if constexpr (ZI) {  // truncated rows enter the inverse as zeros
-#pragma unroll
-                for (int j = 0; j < 3; ++j) acc[j][i] = {0, 0};
-            }
-            continue;
-        }
-        const int kzi = n <= K ? n : n - N;
+        jz = valid ? compact_of(n, N, K, M) : -1;
+        kzi = n <= K ? n : n - N;
+    };
+    // -i sum_j k_j B_ij (or the transform itself), scaled, then the Leray
+    // projection (not for the adjoint, which acts on the whole cube)
+    auto contracted = [&](int i, int kzi, cpx<R>(&b)[3]) {
         const R kz = (R)kzi;
-        cpx<R> b[3];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             if constexpr (MODE == F3_RHS) b[j] = {acc[j][i].y * sc, -acc[j][i].x * sc};  // -i * sum
             else b[j] = {acc[j][i].x * sc, acc[j][i].y * sc};
         }
+        if constexpr (MODE == F3_ADJ) return;
         const int k2 = kxi * kxi + kyi * kyi + kzi * kzi;
-        const long long st = samp * a.st_ss + (long long)jz * a.MMx + s;
-        if constexpr (MODE == F3_ADJ) {
-            // out = ca L3 + c2 L2 + c1 L1 + cc dt (T a - rate lam), no projection
-            const R rt = rate[k2];
-            const R c3 = (R)a.ca, c2 = (R)a.c2, c1 = (R)a.c1, cdt = (R)(a.cc * dts);
-            const cpx<R>* lam = static_cast<const cpx<R>*>(a.us) + st;
-            cpx<R>* o = static_cast<cpx<R>*>(a.out) + st;
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const cpx<R> w = lam[j * a.st_cs];
-                cpx<R> r = {cdt * (b[j].x - rt * w.x), cdt * (b[j].y - rt * w.y)};
-                if (a.ca != 0.0) {
-                    const cpx<R> z = static_cast<const cpx<R>*>(a.u0)[st + j * a.st_cs];
-                    r.x += c3 * z.x;
-                    r.y += c3 * z.y;
-                }
-                if (a.c2 != 0.0) {
-                    const cpx<R> z = static_cast<const cpx<R>*>(a.l2)[st + j * a.st_cs];
-                    r.x += c2 * z.x;
-                    r.y += c2 * z.y;
-                }
-                if (a.c1 != 0.0) {
-                    const cpx<R> z = static_cast<const cpx<R>*>(a.l1)[st + j * a.st_cs];
-                    r.x += c1 * z.x;
-                    r.y += c1 * z.y;
-                }
-                o[j * a.st_cs] = r;
-            }
-            continue;
-        }
         if (k2 > 0) {
             const R inv = (R)1 / (R)k2;
             const cpx<R> kb = {kx * b[0].x + ky * b[1].x + kz * b[2].x, kx * b[0].y + ky * b[1].y + kz * b[2].y};
@@ -533,30 +658,173 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
                 b[j].y -= kv[j] * kb.y * inv;
             }
         }
-        if constexpr (MODE == F3_RHS) {
-            const R rt = rate[k2];
-            const R ca = (R)a.ca, cb = (R)a.cb, cdt = (R)(a.cc * dts);
-            const cpx<R>* us = static_cast<const cpx<R>*>(a.us) + st;
-            const cpx<R>* u0 = static_cast<const cpx<R>*>(a.u0) + st;
-            cpx<R>* o = static_cast<cpx<R>*>(a.out) + st;
+    };
+    auto st_of = [&](int jz) { return samp * a.st_ss + (long long)jz * a.MMx + s; };
+    auto k2_of = [&](int kzi) { return kxi * kxi + kyi * kyi + kzi * kzi; };
+
+    if constexpr (MODE == F3_PROJ) {
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const cpx<R> w = us[j * a.st_cs];
-                cpx<R> f = {b[j].x - rt * w.x, b[j].y - rt * w.y};
-                cpx<R> r = {cb * w.x + cdt * f.x, cb * w.y + cdt * f.y};
-                if (a.ca != 0.0) {
-                    const cpx<R> w0 = u0[j * a.st_cs];
-                    r.x += ca * w0.x;
-                    r.y += ca * w0.y;
-                }
-                o[j * a.st_cs] = r;
-                if constexpr (ZI) acc[j][i] = r;
-            }
-        } else {
-            cpx<R>* o = static_cast<cpx<R>*>(a.out) + st;
+        for (int i = 0; i < E; ++i) {
+            if (!slot_may_keep<P>(i)) continue;
+            int kzi, jz;
+            row(i, kzi, jz);
+            if (jz < 0) continue;
+            cpx<R> b[3];
+            contracted(i, kzi, b);
+            cpx<R>* o = static_cast<cpx<R>*>(a.out) + st_of(jz);
 #pragma unroll
             for (int j = 0; j < 3; ++j) o[j * a.st_cs] = b[j];
         }
+    } else if constexpr (MODE == F3_RHS) {
+        // out = ca u0 + cb us + cc dt F, F = c - rate us; u0 is read only when
+        // ca != 0 (uniform over the launch)
+        auto epilogue = [&](auto with_u0) {
+            constexpr bool U0 = decltype(with_u0)::value;
+            const R ca = (R)a.ca, cb = (R)a.cb, cdt = (R)(a.cc * dts);
+            const cpx<R>* __restrict__ us = static_cast<const cpx<R>*>(a.us);
+            const cpx<R>* __restrict__ u0 = static_cast<const cpx<R>*>(a.u0);
+            cpx<R>* o = static_cast<cpx<R>*>(a.out);
+            constexpr int GS = U0 ? E / 2 : E;  // slots per load group (registers)
+#pragma unroll
+            for (int i0 = 0; i0 < E; i0 += GS) {
+                cpx<R> w[GS][3], w0[U0 ? GS : 1][3];
+                R rt[GS];
+#pragma unroll
+                for (int d = 0; d < GS; ++d) {
+                    const int i = i0 + d;
+                    if (i >= E || !slot_may_keep<P>(i)) continue;
+                    int kzi, jz;
+                    row(i, kzi, jz);
+                    if (jz < 0) continue;
+                    const long long st = st_of(jz);
+                    rt[d] = rate[k2_of(kzi)];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        w[d][j] = us[st + j * a.st_cs];
+                        if constexpr (U0) w0[d][j] = u0[st + j * a.st_cs];
+                    }
+                }
+#pragma unroll
+                for (int d = 0; d < GS; ++d) {
+                    const int i = i0 + d;
+                    if (i >= E) continue;
+                    if (!slot_may_keep<P>(i)) {
+                        if constexpr (ZI) {  // truncated rows enter the inverse as zeros
+#pragma unroll
+                            for (int j = 0; j < 3; ++j) acc[j][i] = {0, 0};
+                        }
+                        continue;
+                    }
+                    int kzi, jz;
+                    row(i, kzi, jz);
+                    if (jz < 0) {
+                        if constexpr (ZI) {
+#pragma unroll
+                            for (int j = 0; j < 3; ++j) acc[j][i] = {0, 0};
+                        }
+                        continue;
+                    }
+                    cpx<R> b[3];
+                    contracted(i, kzi, b);
+                    const long long st = st_of(jz);
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const cpx<R> ww = w[d][j];
+                        cpx<R> f = {b[j].x - rt[d] * ww.x, b[j].y - rt[d] * ww.y};
+                        cpx<R> r = {cb * ww.x + cdt * f.x, cb * ww.y + cdt * f.y};
+                        if constexpr (U0) {
+                            r.x += ca * w0[d][j].x;
+                            r.y += ca * w0[d][j].y;
+                        }
+                        o[st + j * a.st_cs] = r;
+                        if constexpr (ZI) acc[j][i] = r;
+                    }
+                }
+            }
+        };
+        if (a.ca != 0.0) epilogue(std::true_type{});
+        else epilogue(std::false_type{});
+    } else {  // F3_ADJ
+        // out = ca L3 + c2 L2 + c1 L1 + cc dt (T a - rate lam), no projection;
+        // L3 = u0, lam = us.  A term with a zero coefficient is not read, and
+        // L1 is not read again when it is lam itself.
+        auto epilogue = [&](auto with3, auto with2, auto with1) {
+            constexpr bool H3 = decltype(with3)::value, H2 = decltype(with2)::value, H1 = decltype(with1)::value;
+            const R c3 = (R)a.ca, c2 = (R)a.c2, c1 = (R)a.c1, cdt = (R)(a.cc * dts);
+            const bool l1_is_lam = a.l1 == a.us;
+            const cpx<R>* __restrict__ lam = static_cast<const cpx<R>*>(a.us);
+            const cpx<R>* __restrict__ L3 = static_cast<const cpx<R>*>(a.u0);
+            const cpx<R>* __restrict__ L2 = static_cast<const cpx<R>*>(a.l2);
+            const cpx<R>* __restrict__ L1 = static_cast<const cpx<R>*>(H1 ? (l1_is_lam ? a.us : a.l1) : a.us);
+            cpx<R>* o = static_cast<cpx<R>*>(a.out);
+            constexpr int NL = 1 + H3 + H2 + H1;
+            constexpr int GS = NL <= 1 ? E : (NL == 2 ? E / 2 : E / 4 > 0 ? E / 4 : 1);
+#pragma unroll
+            for (int i0 = 0; i0 < E; i0 += GS) {
+                cpx<R> wl[GS][3], w3[H3 ? GS : 1][3], w2[H2 ? GS : 1][3], w1[H1 ? GS : 1][3];
+                R rt[GS];
+#pragma unroll
+                for (int d = 0; d < GS; ++d) {
+                    const int i = i0 + d;
+                    if (i >= E || !slot_may_keep<P>(i)) continue;
+                    int kzi, jz;
+                    row(i, kzi, jz);
+                    if (jz < 0) continue;
+                    const long long st = st_of(jz);
+                    rt[d] = rate[k2_of(kzi)];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        wl[d][j] = lam[st + j * a.st_cs];
+                        if constexpr (H3) w3[d][j] = L3[st + j * a.st_cs];
+                        if constexpr (H2) w2[d][j] = L2[st + j * a.st_cs];
+                        if constexpr (H1) {
+                            if (!l1_is_lam) w1[d][j] = L1[st + j * a.st_cs];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int d = 0; d < GS; ++d) {
+                    const int i = i0 + d;
+                    if (i >= E || !slot_may_keep<P>(i)) continue;
+                    int kzi, jz;
+                    row(i, kzi, jz);
+                    if (jz < 0) continue;
+                    cpx<R> b[3];
+                    contracted(i, kzi, b);
+                    const long long st = st_of(jz);
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const cpx<R> w = wl[d][j];
+                        cpx<R> r = {cdt * (b[j].x - rt[d] * w.x), cdt * (b[j].y - rt[d] * w.y)};
+                        if constexpr (H3) {
+                            r.x += c3 * w3[d][j].x;
+                            r.y += c3 * w3[d][j].y;
+                        }
+                        if constexpr (H2) {
+                            r.x += c2 * w2[d][j].x;
+                            r.y += c2 * w2[d][j].y;
+                        }
+                        if constexpr (H1) {
+                            const cpx<R> z = l1_is_lam ? w : w1[d][j];
+                            r.x += c1 * z.x;
+                            r.y += c1 * z.y;
+                        }
+                        o[st + j * a.st_cs] = r;
+                    }
+                }
+            }
+        };
+        using T_ = std::true_type;
+        using F_ = std::false_type;
+        const bool h3 = a.ca != 0.0, h2 = a.c2 != 0.0, h1 = a.c1 != 0.0;
+        if (h3 && !h2 && !h1) epilogue(T_{}, F_{}, F_{});
+        else if (!h3 && h2 && !h1) epilogue(F_{}, T_{}, F_{});
+        else if (h3 && h2 && h1) epilogue(T_{}, T_{}, T_{});
+        else if (h3 && h2) epilogue(T_{}, T_{}, F_{});
+        else if (h3 && h1) epilogue(T_{}, F_{}, T_{});
+        else if (h2 && h1) epilogue(F_{}, T_{}, T_{});
+        else if (h1) epilogue(F_{}, F_{}, T_{});
+        else epilogue(F_{}, F_{}, F_{});
     }
     if constexpr (ZI) {
         // acc[j][i] holds row out_pos(g, i) of component j of the new state
@@ -578,14 +846,18 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
                 acc[0][i] = acc[1][i];
                 acc[1][i] = acc[2][i];
             }
-            if constexpr (SP) P::template run<+1, T, 1>(v, gg, reinterpret_cast<cpx<R>*>(reinterpret_cast<R*>(lds) + cc), twl);
-            else P::template run<+1, T, 0>(v, gg, lds + cc, twl);
+            fft(std::integral_constant<int, +1>{}, v, gg, cc);
             if (valid) {
 #pragma unroll
                 for (int i = 0; i < E; ++i) zo[j * a.in_cs + (long long)P::out_pos(gg, i) * a.MMx] = v[i];
             }
         }
     }
+    };  // tile_body
+
+    const Col col = column(xcd_tile(gridDim.x));
+    if constexpr (PRE) load(0, nxt, g, col);
+    tile_body(col);
 }
 
 // ------------------------------------------------------------------ launch
@@ -613,15 +885,15 @@ inline bool cut_ok(int K, int M)
 
 // Launchers of one schedule each.  W is the minimum number of waves per
 // SIMD the compiler must allow (it caps the registers per thread).
-template <class P, int T, int DIR, int MODE, int SP, int W, typename R>
+template <class P, int T, int DIR, int MODE, int SP, int W, typename R, int DB = 0>
 hipError_t launch_col(const ColArgs& a, hipStream_t s)
 {
+    constexpr size_t lds = (DB ? 2 : 1) * tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len;
     static_assert(P::G * T <= 1024, "at most 1024 threads per block");
-    static_assert(tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len <= 163840, "LDS per block exceeds 160 KiB");
+    static_assert(lds <= 163840, "LDS per block exceeds 160 KiB");
     static bool done = false;
     if (!cut_ok<P::N>(a.K, a.M)) return hipErrorInvalidValue;
-    return launch_k(k_colfft<P, T, DIR, MODE, SP, W, R>, (a.Q + T - 1) / T, P::G * T,
-                    tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len, s, a, done);
+    return launch_k(k_colfft<P, T, DIR, MODE, SP, W, R, DB>, (a.Q + T - 1) / T, P::G * T, lds, s, a, done);
 }
 
 inline int device_cus()
@@ -649,7 +921,7 @@ hipError_t launch_col_p(const ColArgs& a, hipStream_t s)
                     tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len, s, a, done);
 }
 
-template <class PI, class PF, int U, int MODE, int W, typename R, int BPC = 0>
+template <class PI, class PF, int U, int MODE, int W, typename R, int BPC = 0, bool WS = false>
 hipError_t launch_x(const XArgs& a, hipStream_t s)
 {
     constexpr int XL = x_line_len<PI, PF, R>();
@@ -660,20 +932,33 @@ hipError_t launch_x(const XArgs& a, hipStream_t s)
     if (a.K != Cut<PI::N>::K) return hipErrorInvalidValue;
     long long grid = (a.nunits + U - 1) / U;
     if (BPC > 0 && grid > (long long)device_cus() * BPC) grid = (long long)device_cus() * BPC;
-    return launch_k(k_xline<PI, PF, U, MODE, W, R, BPC>, grid, PI::G * U,
+    return launch_k(k_xline<PI, PF, U, MODE, W, R, BPC, WS>, grid, PI::G * U,
                     sizeof(cpx<R>) * (XL * U + TW), s, a, done);
 }
 
-template <class P, int T, int MODE, int SP, int W, typename R, int PRE = 0, int ZI = 0>
+// x pass in the half-length form: a.nunits pairs of lines, i.e. 2 a.nunits lines
+template <class PH, int U, int W, typename R>
+hipError_t launch_xh(const XArgs& a, hipStream_t s)
+{
+    constexpr int LL = PH::template lds_len_st<sizeof(cpx<R>)>();
+    constexpr size_t lds = sizeof(cpx<R>) * ((size_t)LL * U + PH::tw_len);
+    static_assert(PH::G * U <= 1024, "at most 1024 threads per block");
+    static_assert(lds <= 163840, "LDS per block exceeds 160 KiB");
+    static bool done = false;
+    if (a.K != (2 * PH::N - 1) / 3) return hipErrorInvalidValue;
+    return launch_k(k_xhalf<PH, U, W, R>, (2 * a.nunits + U - 1) / U, PH::G * U, lds, s, a, done);
+}
+
+template <class P, int T, int MODE, int SP, int W, typename R, int PRE = 0, int ZI = 0, int DB = 0>
 hipError_t launch_f3(const F3Args& a, hipStream_t s)
 {
+    constexpr size_t lds = (DB ? 2 : 1) * tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len;
     static_assert(P::G * T <= 1024, "at most 1024 threads per block");
-    static_assert(tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len <= 163840, "LDS per block exceeds 160 KiB");
+    static_assert(lds <= 163840, "LDS per block exceeds 160 KiB");
     static bool done = false;
     if (!cut_ok<P::N>(a.K, a.M) || a.Mx != Cut<P::N>::K + 1) return hipErrorInvalidValue;
     if (ZI && !a.zinv) return hipErrorInvalidValue;
-    return launch_k(k_f3<P, T, MODE, SP, W, R, PRE, ZI>, (a.Q + T - 1) / T, P::G * T,
-                    tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len, s, a, done);
+    return launch_k(k_f3<P, T, MODE, SP, W, R, PRE, ZI, DB>, (a.Q + T - 1) / T, P::G * T, lds, s, a, done);
 }
 
 template <class V, class F>

@@ -11,6 +11,8 @@ using PC = Plan<1024, 64, Radices<16, 16, 4>>;
 using PCR = Plan<1024, 64, Radices<4, 16, 16>>;
 using PD = Plan<1024, 256, Radices<4, 4, 4, 4, 4>>;
 using PE = Plan<1024, 128, Radices<4, 8, 8, 4>>;
+using PAR = Plan<1024, 64, Radices<4, 16, 16>>;
+using PH = Plan<512, 64, Radices<8, 8, 8>>;  // half-length x lines
 
 SizeKernels make32()
 {
@@ -31,12 +33,16 @@ SizeKernels make32()
     add_x<PD, PD, 2, 1, R>(k, "G256 r4.4.4.4.4 U2");
     add_x<PD, PD, 1, 1, R>(k, "G256 r4.4.4.4.4 U1");
     add_x<PE, PE, 2, 1, R>(k, "G128 r4.8.8.4 U2");
+    add_xh<PH, 4, 1, R>(k, "half G64 r8.8.8 U4");
+    add_xh<PH, 4, 4, R>(k, "half G64 r8.8.8 U4 w4");
     add_f3<PB, 4, 1, 1, R, 1>(k, "G128 r8.8.4.4 T4 split prefetch");
     add_f3<PB, 8, 0, 1, R, 1>(k, "G128 r8.8.4.4 T8 prefetch");
     add_f3<PE, 8, 0, 1, R, 1>(k, "G128 r4.8.8.4 T8 prefetch");
     add_f3<PB, 8, 1, 1, R, 1>(k, "G128 r8.8.4.4 T8 split prefetch");
     add_f3<PC, 8, 1, 1, R>(k, "G64 r16.16.4 T8 split");
     add_f3<PD, 4, 0, 1, R, 1>(k, "G256 r4.4.4.4.4 T4 prefetch");
+    // double-buffered exchanges: one barrier per exchange
+    add_f3<PB, 8, 0, 1, R, 1, 1>(k, "G128 r8.8.4.4 T8 prefetch db");
     return k;
 }
 

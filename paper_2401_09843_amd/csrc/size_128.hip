@@ -9,6 +9,7 @@ using PB = Plan<128, 16, Radices<8, 8, 2>>;
 using PBR = Plan<128, 16, Radices<2, 8, 8>>;
 using PC = Plan<128, 32, Radices<4, 4, 4, 2>>;
 using PCR = Plan<128, 32, Radices<2, 4, 4, 4>>;
+using PH = Plan<64, 8, Radices<8, 8>>;  // half-length x lines
 
 SizeKernels make32()
 {
@@ -20,6 +21,11 @@ SizeKernels make32()
     add_x<PB, PBR, 8, 1, R>(k, "G16 r8.8.2 U8");
     add_x<PC, PCR, 4, 1, R>(k, "G32 r4.4.4.2 U4");
     add_x<PA, Plan<128, 8, Radices<8, 16>>, 16, 1, R>(k, "G8 r16.8 U16");
+    add_x_ws<PB, PBR, 8, 1, R>(k, "G16 r8.8.2 U8 wave");
+    add_x_ws<PA, Plan<128, 8, Radices<8, 16>>, 16, 1, R>(k, "G8 r16.8 U16 wave");
+    add_x_ws<PC, PCR, 4, 1, R>(k, "G32 r4.4.4.2 U4 wave");
+    add_xh<PH, 16, 1, R>(k, "half G8 r8.8 U16");
+    add_xh<PH, 32, 1, R>(k, "half G8 r8.8 U32");
     add_f3<PB, 8, 0, 1, R>(k, "G16 r8.8.2 T8");
     add_f3<PA, 16, 0, 1, R>(k, "G8 r16.8 T16");
     add_f3<PC, 8, 0, 1, R>(k, "G32 r4.4.4.2 T8");

@@ -8,6 +8,7 @@ using PA = Plan<256, 16, Radices<16, 16>>;
 using PB = Plan<256, 32, Radices<8, 8, 4>>;
 using PBR = Plan<256, 32, Radices<4, 8, 8>>;
 using PC = Plan<256, 64, Radices<4, 4, 4, 4>>;
+using PH = Plan<128, 16, Radices<8, 2, 8>>;  // half-length x lines
 
 SizeKernels make32()
 {
@@ -23,6 +24,9 @@ SizeKernels make32()
     add_x<PB, PBR, 8, 1, R>(k, "G32 r8.8.4 U8");
     add_x<PA, PA, 4, 1, R>(k, "G16 r16.16 U4");
     add_x<PA, PA, 8, 1, R>(k, "G16 r16.16 U8");
+    add_x_ws<PB, PBR, 4, 1, R>(k, "G32 r8.8.4 U4 wave");
+    add_x_ws<PA, PA, 8, 1, R>(k, "G16 r16.16 U8 wave");
+    add_xh<PH, 16, 1, R>(k, "half G16 r8.2.8 U16");
     add_f3<PB, 4, 0, 1, R>(k, "G32 r8.8.4 T4");
     add_f3<PB, 16, 0, 1, R>(k, "G32 r8.8.4 T16");
     add_f3<PA, 16, 0, 1, R>(k, "G16 r16.16 T16");

@@ -9,6 +9,7 @@ using PB = Plan<512, 32, Radices<16, 8, 4>>;
 using PBR = Plan<512, 32, Radices<4, 8, 16>>;
 using PC = Plan<512, 128, Radices<4, 4, 4, 4, 2>>;
 using PCR = Plan<512, 128, Radices<2, 4, 4, 4, 4>>;
+using PH = Plan<256, 32, Radices<8, 4, 8>>;  // half-length x lines
 
 SizeKernels make32()
 {
@@ -24,6 +25,10 @@ SizeKernels make32()
     add_x<PA, PA, 4, 3, R>(k, "G64 r8.8.8 U4 w3");
     add_x<PB, PBR, 4, 1, R>(k, "G32 r16.8.4 U4");
     add_x<PC, PCR, 2, 1, R>(k, "G128 r4.4.4.4.2 U2");
+    add_x_ws<PA, PA, 2, 1, R>(k, "G64 r8.8.8 U2 wave");
+    add_x_ws<PA, PA, 4, 3, R>(k, "G64 r8.8.8 U4 wave w3");
+    add_x_ws<PB, PBR, 4, 1, R>(k, "G32 r16.8.4 U4 wave");
+    add_xh<PH, 8, 1, R>(k, "half G32 r8.4.8 U8");
     add_f3<PA, 4, 0, 1, R>(k, "G64 r8.8.8 T4");
     add_f3<PA, 8, 1, 1, R>(k, "G64 r8.8.8 T8 split");
     add_f3<PC, 4, 0, 1, R>(k, "G128 r4.4.4.4.2 T4");

@@ -18,18 +18,32 @@ void add_col_p(SizeKernels& k, const char* name)
     add_variant(k.fwd, k.n_fwd, launch_col_p<P, T, -1, COL_FWD_TRUNC, SP, W, BPC, R>, name);
 }
 
-template <class PI, class PF, int U, int W, typename R, int BPC = 0>
+template <class PI, class PF, int U, int W, typename R, int BPC = 0, bool WS = false>
 void add_x(SizeKernels& k, const char* name)
 {
-    add_variant(k.x, k.n_x, launch_x<PI, PF, U, X_RHS, W, R, BPC>, name);
+    add_variant(k.x, k.n_x, launch_x<PI, PF, U, X_RHS, W, R, BPC, WS>, name);
 }
 
-template <class P, int T, int SP, int W, typename R, int PRE = 0>
+// the x pass in the half-length form (one wavefront per line)
+template <class PH, int U, int W, typename R>
+void add_xh(SizeKernels& k, const char* name)
+{
+    add_variant(k.x, k.n_x, launch_xh<PH, U, W, R>, name);
+}
+
+// the x pass with wavefront-synchronous exchanges (lines of at most 64 threads)
+template <class PI, class PF, int U, int W, typename R>
+void add_x_ws(SizeKernels& k, const char* name)
+{
+    add_variant(k.x, k.n_x, launch_x<PI, PF, U, X_RHS, W, R, 0, true>, name);
+}
+
+template <class P, int T, int SP, int W, typename R, int PRE = 0, int DB = 0>
 void add_f3(SizeKernels& k, const char* name)
 {
     const int before = k.n_f3;
-    add_variant(k.f3, k.n_f3, launch_f3<P, T, F3_RHS, SP, W, R, PRE>, name);
-    if (k.n_f3 > before) k.f3[k.n_f3 - 1].fn_zi = launch_f3<P, T, F3_RHS, SP, W, R, PRE, 1>;
+    add_variant(k.f3, k.n_f3, launch_f3<P, T, F3_RHS, SP, W, R, PRE, 0, DB>, name);
+    if (k.n_f3 > before) k.f3[k.n_f3 - 1].fn_zi = launch_f3<P, T, F3_RHS, SP, W, R, PRE, 1, DB>;
 }
 
 }  // namespace ns
