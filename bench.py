@@ -399,6 +399,22 @@ def ensemble_record(args, steps, warmup, batched_only=False, statistics=False):
         "speedup_vs_loop_on_batched_schedules": t_forced / t_batched,
         "batched_equals_loop_on_batched_schedules_bitwise": bitwise,
     })
+    # each size group alone (same samples, same batched kernels): with the
+    # groups on concurrent graph branches the step costs about the larger one
+    alone = {}
+    for n in sorted(set(ENS_SIZES)):
+        idx = [i for i, m in enumerate(ENS_SIZES) if m == n]
+        Sg = ns.Solver([n] * len(idx), dtype=torch.float32, graph=True, tune=not args.no_tune,
+                       tune_cache=args.tune_cache, fuse=fuse_arg(args))
+        xs = [init[i].clone() for i in idx]
+        Sg.step(xs, [dts[i] for i in idx], warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Sg.step(xs, [dts[i] for i in idx], steps)
+        torch.cuda.synchronize()
+        alone[str(n)] = (time.perf_counter() - t0) / steps * 1e3
+        Sg.close()
+    rec["group_alone_ms_per_step"] = alone
     if statistics:
         rec.update(ensemble_statistics(E, uhs))
     return rec, E, uhs

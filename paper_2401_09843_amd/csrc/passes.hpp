@@ -566,24 +566,8 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
 #pragma unroll
         for (int i = 0; i < E; ++i) acc[j][i] = {0, 0};
 
-    // the three-component modes unroll the loop: a runtime component index
-    // would turn the assignment into acc[p] and push acc to scratch memory
-    constexpr int UNR = MODE == F3_RHS ? 1 : NC;
-#pragma unroll UNR
-    for (int p = 0; p < NC; ++p) {
-        // opaque copies of the thread coordinates: the addresses derived
-        // from them are recomputed per component instead of being hoisted
-        // out of the loop, which would hold them in registers throughout
-        int gg = g, cc = c;
-        asm volatile("" : "+v"(gg), "+v"(cc));
-        cpx<R> v[E];
-        if constexpr (PRE) {
-#pragma unroll
-            for (int i = 0; i < E; ++i) v[i] = nxt[i];
-            if (p + 1 < NC) load(p + 1, nxt, gg, col);
-        } else {
-            load(p, v, gg, col);
-        }
+    // transform of component p (in v) and its accumulation
+    auto component = [&](int p, cpx<R>(&v)[E], int gg, int cc) {
         fft(std::integral_constant<int, -1>{}, v, gg, cc);
         if constexpr (MODE == F3_RHS) {
             // component p = (i, j) of the upper triangle adds k_j B to b_i
@@ -619,6 +603,29 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
                 acc[1][i] = p == 1 ? v[i] : acc[1][i];
                 acc[2][i] = p == 2 ? v[i] : acc[2][i];
             }
+        }
+    };
+
+    {
+        // the three-component modes unroll the loop: a runtime component index
+        // would turn the assignment into acc[p] and push acc to scratch memory
+        constexpr int UNR = MODE == F3_RHS ? 1 : NC;
+#pragma unroll UNR
+        for (int p = 0; p < NC; ++p) {
+            // opaque copies of the thread coordinates: the addresses derived
+            // from them are recomputed per component instead of being hoisted
+            // out of the loop, which would hold them in registers throughout
+            int gg = g, cc = c;
+            asm volatile("" : "+v"(gg), "+v"(cc));
+            cpx<R> v[E];
+            if constexpr (PRE) {
+#pragma unroll
+                for (int i = 0; i < E; ++i) v[i] = nxt[i];
+                if (p + 1 < NC) load(p + 1, nxt, gg, col);
+            } else {
+                load(p, v, gg, col);
+            }
+            component(p, v, gg, cc);
         }
     }
 

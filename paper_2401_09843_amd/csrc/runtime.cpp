@@ -715,7 +715,9 @@ ns_status tune_group(ns_ctx* c, Group& g)
             if (e != hipSuccess) st = fail(c, NS_ERR_HIP, "timing the stage forms failed: %s", hipGetErrorString(e));
             g.stage_ms[zi] = std::min(g.stage_ms[zi], ms);
         }
-        g.fuse = g.stage_ms[1] < g.stage_ms[0];
+        // the fused form must win by more than 1 %: within timing noise the
+        // plain form is kept, so that the choice does not flip between runs
+        g.fuse = g.stage_ms[1] < 0.99 * g.stage_ms[0];
     }
     const int form = g.fuse ? 1 : 0;
     g.sel[4] = best_f3[form];

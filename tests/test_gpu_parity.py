@@ -60,6 +60,23 @@ def test_rhs_matches_oracle(ns, orc, n, dtype):
     got = to_np(S.rhs(to_dev(uh, dtype)))
     torch.cuda.synchronize()
     assert rel(got, ref) <= TOL[dtype]
+    # per mode, and on the low-energy subsets an error could hide in under a
+    # whole-array norm: the k_x = 0 plane (its Hermitian handling) and the
+    # faces of the retained cube (the cutoff)
+    K = (n - 1) // 3
+    kz = np.abs(np.fft.fftfreq(n, 1.0 / n))[:, None, None]
+    ky = np.abs(np.fft.fftfreq(n, 1.0 / n))[None, :, None]
+    kx = np.arange(n // 2 + 1)[None, None, :]
+    faces = ((kz == K) | (ky == K) | (kx == K)) & (kz <= K) & (ky <= K) & (kx <= K)
+    faces = np.broadcast_to(faces, got.shape[1:])
+    plane0 = np.zeros(got.shape[1:], dtype=bool)
+    plane0[:, :, 0] = True
+    e_max = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    e_face = rel(got[:, faces], ref[:, faces])
+    e_plane = rel(got[:, plane0], ref[:, plane0])
+    print("  per-mode max %.2e, cutoff faces %.2e, k_x = 0 plane %.2e" % (e_max, e_face, e_plane), flush=True)
+    assert e_max <= TOL[dtype]
+    assert e_face <= 10 * TOL[dtype] and e_plane <= 10 * TOL[dtype]
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
