@@ -128,30 +128,34 @@ def fuse_arg(args):
 
 
 def kernel_source_hash() -> str:
-    """SHA-256 of the HIP sources; PMC traffic figures are valid only for
-    the kernels they were measured on."""
+    """SHA-256 of the device-code sources (the kernels, their launchers and
+    the per-size schedules; not the host runtime); PMC traffic figures are
+    valid only for the kernels they were measured on."""
     import glob
     import hashlib
 
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2401_09843_amd", "csrc", "*"))):
+    csrc = os.path.join(ROOT, "paper_2401_09843_amd", "csrc")
+    for p in sorted(glob.glob(os.path.join(csrc, "*.hpp")) + glob.glob(os.path.join(csrc, "*.hip"))):
         with open(p, "rb") as f:
             h.update(os.path.basename(p).encode())
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, n: int, variant: str):
+def measured_traffic(kernel: str, n: int, variant: str, stage_form: str):
     """HBM bytes per launch of a pass from the committed rocprofv3 PMC
     summary (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel
     calibration), or None if there is none, the kernels changed since, or
-    the figure belongs to another schedule variant than the one timed."""
+    the figure belongs to another schedule variant or stage form than the
+    one timed."""
     path = os.path.join(PROFILE_DIR, "traffic_%s_n%d.json" % (kernel, n))
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_hash") != kernel_source_hash() or d.get("variant") != variant:
+    if (d.get("source_hash") != kernel_source_hash() or d.get("variant") != variant
+            or d.get("stage_form") != stage_form):
         return None
     return d.get("bytes_per_launch")
 
@@ -232,7 +236,7 @@ def plain_run(args, n, dtype, steps, warmup, profile=True, keep=False, tune=True
                 per_pass[name] = {"avg_ms": avg, "launches": cnt, "GBps": bpl[name] / (avg * 1e-3) / 1e9}
         dom = max(per_pass, key=lambda k: per_pass[k]["avg_ms"] * per_pass[k]["launches"])
         ach = per_pass[dom]["GBps"]
-        traffic = None if pad else measured_traffic(dom, n, schedule.get(dom))
+        traffic = None if pad else measured_traffic(dom, n, schedule.get(dom), "fused" if fused else "plain")
         roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                     "traffic": traffic, "kernel": dom, "algorithmic_bytes_per_launch": bpl[dom]}
     step_bytes = perfmodel.step_bytes(grid, rbytes, fused=fused, steps_per_call=steps)
