@@ -353,6 +353,10 @@ def ensemble_record(args, steps, warmup, batched_only=False, statistics=False):
         "step_roofline_frac": ens_bytes / (t_batched / steps) / 1e9 / HBM_PEAK_GBS,
         "schedule": report,
     }
+    f3 = [r for r in report if r["pass"] == "F3_fwd_z_epilogue"]
+    if f3 and "graph_form" in f3[0]:
+        rec["graph_form"] = f3[0]["graph_form"]
+        rec["graph_form_ms_per_step"] = f3[0]["graph_ms"]
     if batched_only:
         return rec, E, uhs
     # the baseline: plain solvers autotuned at one sample, warmed up per size
@@ -403,8 +407,8 @@ def ensemble_record(args, steps, warmup, batched_only=False, statistics=False):
         "speedup_vs_loop_on_batched_schedules": t_forced / t_batched,
         "batched_equals_loop_on_batched_schedules_bitwise": bitwise,
     })
-    # each size group alone (same samples, same batched kernels): with the
-    # groups on concurrent graph branches the step costs about the larger one
+    # each size group alone (same samples, same batched kernels): against
+    # the batched step, whether the size groups overlap at all
     alone = {}
     for n in sorted(set(ENS_SIZES)):
         idx = [i for i, m in enumerate(ENS_SIZES) if m == n]

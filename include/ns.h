@@ -85,6 +85,15 @@ typedef enum { NS_F32 = 0, NS_F64 = 1 } ns_dtype;
                                ignored on input and written as zero.  Physical fields
                                (ns_forward, ns_inverse) live on the 3n/2 grid; eps and
                                m_cut defaults are taken at n. */
+#define NS_GRAPH_CHAIN    64u  /* with NS_USE_GRAPH and several grid sizes: the captured
+                                  step runs the size groups one after another on one
+                                  stream */
+#define NS_GRAPH_BRANCHES 128u /* ... or as concurrent graph branches.  With neither flag
+                                  (and without NS_NO_TUNE) ns_init times both forms on
+                                  seeded states and keeps the branches only if they win
+                                  by more than 1 %; with NS_NO_TUNE: the chain.  The two
+                                  flags exclude each other; results are bitwise the same
+                                  in either form. */
 
 /* Model and run parameters (eqs. (2.1)-(2.4)).
  *   eps    epsilon_N, the hyperviscosity amplitude; < 0 selects the default
@@ -106,7 +115,8 @@ typedef struct {
     double         m_cut;
     int32_t        q_kind;
     double         theta;
-    uint32_t       flags;      /* NS_USE_GRAPH | NS_CHECK_FINITE | NS_NO_TUNE | NS_NO_FUSE | NS_FUSE | NS_PAD */
+    uint32_t       flags;      /* NS_USE_GRAPH | NS_CHECK_FINITE | NS_NO_TUNE | NS_NO_FUSE | NS_FUSE | NS_PAD
+                                  | NS_GRAPH_CHAIN | NS_GRAPH_BRANCHES */
     const char*    tune_cache; /* autotuner cache file (JSON) or NULL */
 } ns_params;
 
@@ -279,8 +289,10 @@ ns_status ns_profile_read(ns_ctx* ctx, double* ms, int64_t* count);
  * ns_set_variant overrides the choice (e.g. to test every variant; a pass 4
  * variant is used in the group's stage form); ns_tune_report writes the
  * choices and timings as JSON into buf, with the stage form ("fused") and
- * the stage timings on each pass-4 entry (always NUL-terminated; *needed
- * receives the full length + 1). */
+ * the stage timings on each pass-4 entry, and with several grid sizes the
+ * graph launch form ("graph_form": "chain" or "branches", and its timings
+ * "graph_ms", 0 when not timed) on those entries too (always
+ * NUL-terminated; *needed receives the full length + 1). */
 ns_status ns_variant_count(ns_ctx* ctx, int32_t n, int32_t pass, int32_t* count);
 ns_status ns_set_variant(ns_ctx* ctx, int32_t n, int32_t pass, int32_t variant);
 ns_status ns_tune_report(ns_ctx* ctx, char* buf, size_t len, size_t* needed);

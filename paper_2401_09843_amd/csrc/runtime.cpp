@@ -132,6 +132,10 @@ struct ns_ctx {
     bool failed = false;
     hipGraphExec_t step_exec = nullptr;
     hipGraph_t step_graph = nullptr;
+    // launch form of the captured step with several size groups: one chain
+    // on a single stream, or concurrent branches; graph_ms: their timings
+    bool graph_branches = false;
+    double graph_ms[2] = {0.0, 0.0};
     std::string tune_cache;
     double* edev = nullptr;  // energy check scratch
     // pass profiler: events bracketing each launch while enabled
@@ -728,14 +732,21 @@ ns_status tune_group(ns_ctx* c, Group& g)
     return st;
 }
 
-// One SSP-RK3 step of all groups captured as a graph: group 0 on the
-// capture stream, every further group on a branch stream forked from it and
-// joined back, so groups of different N run concurrently on replay.
+// One SSP-RK3 step of all groups captured as a graph.  As a chain, every
+// group runs on the capture stream in turn.  As branches, group 0 runs on
+// the capture stream and every further group on a branch stream forked from
+// it and joined back, so groups of different N run concurrently on replay.
 ns_status capture_step(ns_ctx* c)
 {
-    const size_t ng = c->groups.size();
+    const size_t ng = c->graph_branches ? c->groups.size() : 1;
     hipStream_t main = c->cap_stream;
     ns_status st = NS_OK;
+    if (!c->graph_branches) {
+        c->stream = main;
+        for (Group& g : c->groups)
+            if ((st = rk3_step(c, g))) return st;
+        return NS_OK;
+    }
     if (ng > 1) {
         HIP_TRY(c, hipEventRecord(c->branch_ev[0], main));
         for (size_t g = 1; g < ng; ++g) HIP_TRY(c, hipStreamWaitEvent(c->branch[g - 1], c->branch_ev[0], 0));
@@ -785,6 +796,64 @@ ns_status ensure_graph(ns_ctx* c)
     if (e != hipSuccess) return fail(c, NS_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
     c->step_graph = graph;
     HIP_TRY(c, hipGraphInstantiate(&c->step_exec, graph, nullptr, nullptr, 0));
+    return NS_OK;
+}
+
+ns_status drop_graph(ns_ctx* c)
+{
+    if (!c->step_exec) return NS_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    (void)hipGraphExecDestroy(c->step_exec);
+    (void)hipGraphDestroy(c->step_graph);
+    c->step_exec = nullptr;
+    c->step_graph = nullptr;
+    return NS_OK;
+}
+
+// The launch form of the captured step with several size groups, timed both
+// ways on seeded states with dt = 0 (alternated, best of two each).  The
+// branches are kept only if they win by more than 1 %: groups that each
+// saturate HBM gain nothing from running side by side.  The states are left
+// holding the seeded values; every stepping call packs its input first.
+ns_status tune_graph_form(ns_ctx* c)
+{
+    hipStream_t s = c->stream;
+    const long long per = (long long)(cwb(c) / c->rsz);  // reals per complex word
+    for (Group& g : c->groups) {
+        HIP_TRY(c, launch_fill_random(c->f64, g.U0, per * (long long)g.st * g.B, 1, s));
+        HIP_TRY(c, launch_fill(g.dt, 0.0, g.B, s));
+        g.dt_host.clear();  // the next set_dt uploads the caller's steps
+        ns_status st = begin_stages(c, g);
+        if (st) return st;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    ns_status st = NS_OK;
+    double best[2] = {1e300, 1e300};
+    for (int r = 0; r < 4 && st == NS_OK; ++r) {
+        c->graph_branches = (r & 1) != 0;
+        if ((st = drop_graph(c)) || (st = ensure_graph(c))) break;
+        hipError_t e = hipGraphLaunch(c->step_exec, s);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipGraphLaunch(c->step_exec, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) st = fail(c, NS_ERR_HIP, "timing the graph forms failed: %s", hipGetErrorString(e));
+        best[r & 1] = std::min(best[r & 1], ms / 3.0);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    c->graph_ms[0] = best[0];
+    c->graph_ms[1] = best[1];
+    const bool branches = best[1] < 0.99 * best[0];
+    if (branches != c->graph_branches) {
+        c->graph_branches = branches;
+        return drop_graph(c);
+    }
     return NS_OK;
 }
 
@@ -916,6 +985,8 @@ ns_status ns_init(const ns_params* p, void* hip_stream, ns_ctx** out)
     if (!std::isfinite(p->eps) || !std::isfinite(p->m_cut)) return fail(nullptr, NS_ERR_ARG, "eps and m_cut must be finite");
     if ((p->flags & NS_NO_FUSE) && (p->flags & NS_FUSE))
         return fail(nullptr, NS_ERR_ARG, "NS_FUSE and NS_NO_FUSE exclude each other");
+    if ((p->flags & NS_GRAPH_CHAIN) && (p->flags & NS_GRAPH_BRANCHES))
+        return fail(nullptr, NS_ERR_ARG, "NS_GRAPH_CHAIN and NS_GRAPH_BRANCHES exclude each other");
     const bool pad = (p->flags & NS_PAD) != 0;
     for (int i = 0; i < p->nsamples; ++i) {
         if (pad && (p->n[i] < 8 || p->n[i] % 2 != 0 || !find_kernels(3 * p->n[i] / 2, p->dtype == NS_F64)))
@@ -957,6 +1028,10 @@ ns_status ns_init(const ns_params* p, void* hip_stream, ns_ctx** out)
     if (st == NS_OK && !(p->flags & NS_NO_TUNE))
         for (Group& g : c->groups)
             if ((st = tune_group(c, g))) break;
+    c->graph_branches = (p->flags & NS_GRAPH_BRANCHES) != 0;
+    if (st == NS_OK && (p->flags & NS_USE_GRAPH) && c->groups.size() > 1 && !(p->flags & NS_NO_TUNE)
+        && !(p->flags & (NS_GRAPH_CHAIN | NS_GRAPH_BRANCHES)))
+        st = tune_graph_form(c);
     if (st == NS_OK) st = dalloc(c, (void**)&c->edev, sizeof(double) * 4096);
     if (st != NS_OK) {
         g_init_error = c->err;
@@ -1027,14 +1102,7 @@ ns_status ns_set_variant(ns_ctx* c, int32_t n, int32_t pass, int32_t variant)
     if (variant < 0 || variant >= variant_count(g->kern, pass))
         return fail(c, NS_ERR_ARG, "variant %d out of range for pass %d at N=%d", variant, pass, n);
     g->sel[pass] = variant;
-    if (c->step_exec) {  // the captured step used the old schedule
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        (void)hipGraphExecDestroy(c->step_exec);
-        (void)hipGraphDestroy(c->step_graph);
-        c->step_exec = nullptr;
-        c->step_graph = nullptr;
-    }
-    return NS_OK;
+    return drop_graph(c);  // the captured step used the old schedule
 }
 
 ns_status ns_tune_report(ns_ctx* c, char* buf, size_t len, size_t* needed)
@@ -1056,6 +1124,9 @@ ns_status ns_tune_report(ns_ctx* c, char* buf, size_t len, size_t* needed)
             if (p == 4)
                 o << ",\"fused\":" << (g.fuse ? "true" : "false") << ",\"stage_ms\":{\"plain\":" << g.stage_ms[0]
                   << ",\"fused\":" << g.stage_ms[1] << "}";
+            if (p == 4 && c->groups.size() > 1)
+                o << ",\"graph_form\":\"" << (c->graph_branches ? "branches" : "chain") << "\",\"graph_ms\":{\"chain\":"
+                  << c->graph_ms[0] << ",\"branches\":" << c->graph_ms[1] << "}";
             o << "}";
         }
     }

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libns.so")
 NS_OK, NS_ERR_ARG, NS_ERR_UNSUPPORTED, NS_ERR_OOM, NS_ERR_HIP, NS_ERR_STATE, NS_ERR_NONFINITE = range(7)
 NS_F32, NS_F64 = 0, 1
 NS_USE_GRAPH, NS_CHECK_FINITE, NS_NO_TUNE, NS_NO_FUSE, NS_FUSE, NS_PAD = 1, 2, 4, 8, 16, 32
+NS_GRAPH_CHAIN, NS_GRAPH_BRANCHES = 64, 128
 
 # every symbol the header declares
 EXPORTS = ("ns_init", "ns_destroy", "ns_last_error", "ns_workspace_bytes", "ns_supported_sizes", "ns_forward",
@@ -121,11 +122,14 @@ class Solver:
     both per grid size (fused if tune is False).
     pad: Algorithm 2 in its padded form.  n is then the number of modes per
     axis of the state (spectra [3, n, n, n//2+1], modes |k_i| <= n/2 - 1) and
-    the passes and physical fields use the grid of 3n/2 points."""
+    the passes and physical fields use the grid of 3n/2 points.
+    graph_form: with several grid sizes, "chain" runs the size groups of the
+    captured step one after another, "branches" as concurrent graph
+    branches; None lets the autotuner time both (chain if tune is False)."""
 
     def __init__(self, n, dtype=torch.float32, eps=-1.0, s=1.5, m_cut=-1.0, q_kind=0, theta=1.0,
                  graph=True, check_finite=False, tune=False, tune_cache=None, stream=None, device=None,
-                 fuse=None, pad=False):
+                 fuse=None, pad=False, graph_form=None):
         self.sizes = [int(n)] if isinstance(n, int) else [int(v) for v in n]
         self.pad = bool(pad)
         self.grids = [3 * v // 2 if self.pad else v for v in self.sizes]
@@ -139,7 +143,8 @@ class Solver:
         nn = (ctypes.c_int32 * len(self.sizes))(*self.sizes)
         flags = ((NS_USE_GRAPH if graph else 0) | (NS_CHECK_FINITE if check_finite else 0)
                  | (0 if tune else NS_NO_TUNE) | {None: 0, True: NS_FUSE, False: NS_NO_FUSE}[fuse]
-                 | (NS_PAD if self.pad else 0))
+                 | (NS_PAD if self.pad else 0)
+                 | {None: 0, "chain": NS_GRAPH_CHAIN, "branches": NS_GRAPH_BRANCHES}[graph_form])
         self._cache = tune_cache.encode() if tune_cache else None
         self._prm = _Params(NS_F32 if dtype == torch.float32 else NS_F64, len(self.sizes), nn, eps, s, m_cut,
                             q_kind, theta, flags, self._cache)

@@ -63,6 +63,10 @@ def test_init_rejects_bad_arguments(ns):
     assert L.ns_init(ctypes.byref(p), None, ctypes.byref(ctx)) == ns.NS_ERR_ARG
     assert b"exclude" in L.ns_last_error(None)
     assert ctx.value is None
+    p.flags = ns.NS_USE_GRAPH | ns.NS_GRAPH_CHAIN | ns.NS_GRAPH_BRANCHES
+    assert L.ns_init(ctypes.byref(p), None, ctypes.byref(ctx)) == ns.NS_ERR_ARG
+    assert b"exclude" in L.ns_last_error(None)
+    assert ctx.value is None
     assert L.ns_destroy(None) == ns.NS_OK
 
 

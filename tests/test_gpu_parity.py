@@ -224,6 +224,42 @@ def test_ensemble_matches_single_samples(ns):
         assert torch.equal(uh, uhs[i]), i
 
 
+def test_ensemble_graph_forms_match_eager_bitwise(ns):
+    """The captured step of an ensemble of three sizes as one chain and as
+    concurrent branches, replayed with eager work in between, gives the bits
+    of eager stepping; a tuned context reports the form it chose and its
+    graph replays give the bits of its own eager steps."""
+    sizes = [32, 16, 32, 24]
+    fields = [inputs.shear_layer(n, seed=20 + i)[0] for i, n in enumerate(sizes)]
+    dts = [inputs.cfl_dt(u) for u in fields]
+    outs = []
+    for kw in (dict(graph=False), dict(graph_form="chain"), dict(graph_form="branches")):
+        E = ns.Solver(sizes, dtype=torch.float32, fuse=True, **kw)
+        uhs = E.forward([to_dev(u, torch.float32) for u in fields])
+        for _ in range(3):
+            E.step(uhs, dts, 2)
+            torch.cuda.synchronize()
+        outs.append([u.cpu() for u in uhs])
+        E.close()
+    for o in outs[1:]:
+        assert all(torch.equal(a, b) for a, b in zip(outs[0], o))
+
+    E = ns.Solver(sizes, dtype=torch.float32, tune=True)
+    rep = [r for r in E.tune_report() if r["pass"] == "F3_fwd_z_epilogue"]
+    assert len(rep) == 3 and len({r["graph_form"] for r in rep}) == 1
+    assert rep[0]["graph_form"] in ("chain", "branches")
+    assert rep[0]["graph_ms"]["chain"] > 0 and rep[0]["graph_ms"]["branches"] > 0
+    res = []
+    for eager in (False, True):
+        E.profile(eager)  # the pass profiler launches the stages eagerly
+        uhs = E.forward([to_dev(u, torch.float32) for u in fields])
+        E.step(uhs, dts, 4)
+        res.append([u.cpu() for u in uhs])
+    E.profile(False)
+    E.close()
+    assert all(torch.equal(a, b) for a, b in zip(res[0], res[1]))
+
+
 def test_paper_families_ensemble_matches_oracle(ns, orc):
     """The paper's initial-data families (Sec. 6) as an ensemble of uneven
     sizes: three perturbed Taylor-Green vortices at 32^3 and two cylindrical
