@@ -161,8 +161,14 @@ ns_status ns_rhs(ns_ctx* ctx, const void* const* uhat_in, void* const* rhs_out);
  * energy is not finite at the end. */
 ns_status ns_step(ns_ctx* ctx, void* const* uhat_inout, const double* dt, int32_t nsteps);
 
-/* Bytes of tape per sample that ns_step_taped writes for nsteps steps. */
+/* Bytes of tape per sample that ns_step_taped writes for nsteps steps (the
+ * largest over the context's grid sizes). */
 ns_status ns_tape_bytes(const ns_ctx* ctx, int32_t nsteps, size_t* per_sample);
+
+/* Bytes of one step of the tape of a sample of size n (as in params->n):
+ * the step stride of that sample's tape, whose step k starts at
+ * k * *bytes.  NS_ERR_ARG if the context holds no sample of size n. */
+ns_status ns_tape_step_bytes(const ns_ctx* ctx, int32_t n, size_t* bytes);
 
 /* As ns_step, and also records each step's three stage states into tape[i]
  * (opaque, ns_tape_bytes(nsteps) bytes per sample), for ns_adjoint_step. */

@@ -6,10 +6,37 @@
 
 namespace ns {
 
+// Compact retained-mode arrays (spectral states, the adjoint's strain): per
+// sample, nc components of the M retained k_z rows of the MMx = M Mx columns
+// s = j_y Mx + k_x.  Columns are stored in blocks of CB neighbours, CB = 64
+// bytes of elements (8 FP32 or 4 FP64 complex values): element (component
+// c, row jz, column s) of a sample lies at
+//     (s / CB) nc M CB + c M CB + jz CB + s % CB,
+// and a sample holds nc M MMxp elements, MMxp = MMx rounded up to CB (the
+// columns beyond MMx are padding, never read as data).  A z pass over a
+// tile of neighbouring columns then reads and writes whole blocks, which
+// are contiguous from one row to the next.
+__host__ __device__ constexpr int compact_cb(int elem_bytes) { return 64 / elem_bytes; }
+__host__ __device__ constexpr int compact_cbl(int elem_bytes) { return elem_bytes == 8 ? 3 : 2; }  // log2 CB
+__host__ __device__ constexpr long long compact_cols(long long MMx, int elem_bytes)
+{
+    return (MMx + compact_cb(elem_bytes) - 1) / compact_cb(elem_bytes) * compact_cb(elem_bytes);
+}
+// offset of (component c, row jz, column s) within one sample
+__host__ __device__ constexpr long long compact_off(int elem_bytes, int nc, int M, int c, int jz, long long s)
+{
+    return (s >> compact_cbl(elem_bytes)) * ((long long)nc * M * compact_cb(elem_bytes)) +
+           (long long)c * M * compact_cb(elem_bytes) + (long long)jz * compact_cb(elem_bytes) +
+           (s & (compact_cb(elem_bytes) - 1));
+}
+
 // Strided-axis C2C pass over columns.  Column q of Q: outer = q / S,
 // inner = q % S, and outer splits into sample b = outer / nc and plane
 // c = outer % nc; element (row r) of the column lives at
-// base + b * ss + c * cs + r * S + inner (complex elements).
+// base + b * ss + c * cs + r * S + inner (complex elements).  An input in
+// the compact layout (in_cbl > 0) is addressed instead as
+// base + b * in_ss + c * in_cs + (inner >> in_cbl) * in_bs + r * in_rs
+// + (inner & (2^in_cbl - 1)).
 struct ColArgs {
     const void* in;
     void* out;
@@ -21,6 +48,8 @@ struct ColArgs {
     long long out_cs, out_ss;  // output plane / sample strides
     int K, M;                  // 2/3 cutoff and compact length 2K+1
     double scale;              // output scale (forward passes)
+    long long in_bs = 0, in_rs = 0;  // input column-block / row strides (in_cbl > 0)
+    int in_cbl = 0;                  // log2 of the input column block, 0: plain rows of S
 };
 
 // x-line pass over pairs of lines.  Line l of a sample is row l of
@@ -37,20 +66,22 @@ struct XArgs {
 };
 
 // z-axis forward pass fused with the right-hand-side / projection epilogue.
-// Columns are the (k_y, k_x) pairs of the compact layout, MMx = M * Mx per
-// sample.
+// Columns are the (k_y, k_x) pairs s of the compact layout, MMx = M * Mx
+// per sample, enumerated as batch * MMxp (MMxp = compact_cols(MMx)); the
+// padding columns s >= MMx are skipped.  States are compact arrays of 3
+// components.
 struct F3Args {
     const void* in;            // [batch][ncomp][N][MMx]
-    const void* u0;            // compact state u^n   [batch][3][M][MMx] (may be null)
-    const void* us;            // compact stage state [batch][3][M][MMx]
-    void* out;                 // compact             [batch][3][M][MMx]
+    const void* u0;            // compact state u^n (may be null)
+    const void* us;            // compact stage state
+    void* out;                 // compact
     const void* tw;
     const void* rate;          // eps |k|^{2s} Q(|k|), indexed by |k|^2
     const double* dt;          // [batch] on the device
-    long long Q;               // batch * MMx
+    long long Q;               // batch * MMxp
     int MMx, Mx, K, M;
     long long in_ss, in_cs;    // input sample / component strides
-    long long st_ss, st_cs;    // state sample / component strides
+    long long st_ss, st_cs;    // state sample stride (3 M MMxp) and component stride in a block (M CB)
     double ca, cb, cc;         // out = ca u0 + cb us + cc dt F
     double scale;
     // adjoint epilogue: out = ca L3 + c2 L2 + c1 L1 + cc dt (a - rate lam)

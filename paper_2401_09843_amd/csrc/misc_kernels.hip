@@ -4,6 +4,7 @@
 // (the energy-spectrum writer of Sec. 2.4).
 #include <cmath>
 
+#include "args.hpp"
 #include "fft_engine.hpp"
 #include "misc_kernels.hpp"
 
@@ -13,7 +14,7 @@ namespace {
 
 __device__ __forceinline__ int full_index(int j, int K, int M, int N) { return j <= K ? j : j - M + N; }
 
-// R2C [3][N][N][N/2+1] -> compact [3][M][M][Mx]
+// R2C [3][N][N][N/2+1] -> compact (the column-blocked layout of args.hpp)
 template <typename R>
 __global__ void k_pack(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out, int N, int K)
 {
@@ -29,7 +30,7 @@ __global__ void k_pack(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out, 
     const int jz = (int)(r % M);
     const int c = (int)(r / M);
     const int nz = full_index(jz, K, M, N), ny = full_index(jy, K, M, N);
-    out[idx] = in[(((long long)c * N + nz) * N + ny) * Nh + kx];
+    out[compact_off(sizeof(cpx<R>), 3, M, c, jz, (long long)jy * Mx + kx)] = in[(((long long)c * N + nz) * N + ny) * Nh + kx];
 }
 
 // compact -> R2C, zero outside the retained cube
@@ -50,7 +51,7 @@ __global__ void k_unpack(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out
     const int jy = ny <= K ? ny : (ny >= N - K ? ny - N + M : -1);
     const int jz = nz <= K ? nz : (nz >= N - K ? nz - N + M : -1);
     cpx<R> v = {0, 0};
-    if (kx <= K && jy >= 0 && jz >= 0) v = in[(((long long)c * M + jz) * M + jy) * Mx + kx];
+    if (kx <= K && jy >= 0 && jz >= 0) v = in[compact_off(sizeof(cpx<R>), 3, M, c, jz, (long long)jy * Mx + kx)];
     out[idx] = v;
 }
 
@@ -165,16 +166,20 @@ __global__ void __launch_bounds__(SPEC_THREADS) k_spectrum(const cpx<R>* __restr
 template <typename R>
 __global__ void k_strain(const cpx<R>* __restrict__ lam, cpx<R>* __restrict__ S, int K, long long batch)
 {
+    constexpr int EB = sizeof(cpx<R>);
     const int M = 2 * K + 1, Mx = K + 1;
-    const long long per = (long long)M * M * Mx;
+    const long long per = (long long)M * M * Mx, cols = compact_cols((long long)M * Mx, EB);
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= per * batch) return;
     const long long b = idx / per, m = idx % per;
+    const long long sc = m % ((long long)M * Mx);
     const int kxi = (int)(m % Mx), jy = (int)((m / Mx) % M), jz = (int)(m / ((long long)Mx * M));
     const int kyi = jy <= K ? jy : jy - M, kzi = jz <= K ? jz : jz - M;
     const R kv[3] = {(R)kxi, (R)kyi, (R)kzi};
-    const cpx<R>* l = lam + b * 3 * per + m;
-    cpx<R> mu[3] = {l[0], l[per], l[2 * per]};
+    // compact offsets: lam has 3 components per sample, S has 6
+    const cpx<R>* l = lam + b * 3 * M * cols + compact_off(EB, 3, M, 0, jz, sc);
+    const long long lcs = compact_off(EB, 3, M, 1, 0, 0);
+    cpx<R> mu[3] = {l[0], l[lcs], l[2 * lcs]};
     const int k2 = kxi * kxi + kyi * kyi + kzi * kzi;
     if (k2 > 0) {
         const R inv = (R)1 / (R)k2;
@@ -186,11 +191,12 @@ __global__ void k_strain(const cpx<R>* __restrict__ lam, cpx<R>* __restrict__ S,
         }
     }
     const int ti[6] = {0, 0, 0, 1, 1, 2}, tj[6] = {0, 1, 2, 1, 2, 2};
-    cpx<R>* o = S + b * 6 * per + m;
+    cpx<R>* o = S + b * 6 * M * cols + compact_off(EB, 6, M, 0, jz, sc);
+    const long long ocs = compact_off(EB, 6, M, 1, 0, 0);
     for (int p = 0; p < 6; ++p) {
         const int i = ti[p], j = tj[p];
         const R wx = kv[i] * mu[j].x + kv[j] * mu[i].x, wy = kv[i] * mu[j].y + kv[j] * mu[i].y;
-        o[p * per] = {(R)-0.5 * wy, (R)0.5 * wx};  // (i/2) w
+        o[p * ocs] = {(R)-0.5 * wy, (R)0.5 * wx};  // (i/2) w
     }
 }
 

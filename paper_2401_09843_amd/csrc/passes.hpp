@@ -60,6 +60,14 @@ constexpr size_t tile_bytes()
     return ((SP ? sizeof(R) : sizeof(cpx<R>)) * P::lds_len * T + 15) / 16 * 16;
 }
 
+// input offset of column `inner` of a plane, and the input row stride
+// (plain rows of S columns, or the column blocks of the compact layout)
+__device__ __forceinline__ long long col_in_off(const ColArgs& a, long long inner)
+{
+    return a.in_cbl ? (inner >> a.in_cbl) * a.in_bs + (inner & ((1LL << a.in_cbl) - 1)) : inner;
+}
+__device__ __forceinline__ long long col_in_rs(const ColArgs& a) { return a.in_cbl ? a.in_rs : a.S; }
+
 // DB = 1 double-buffers the LDS exchanges (one barrier per exchange).
 template <class P, int T, int DIR, int MODE, int SP, int W, typename R, int DB = 0>
 __global__ void __launch_bounds__(P::G* T, W) k_colfft(ColArgs a)
@@ -75,8 +83,9 @@ __global__ void __launch_bounds__(P::G* T, W) k_colfft(ColArgs a)
     const long long outer = valid ? q / a.S : 0;
     const long long inner = valid ? q % a.S : 0;
     const long long sb = outer / a.nc, pc = outer % a.nc;
-    const cpx<R>* __restrict__ in = static_cast<const cpx<R>*>(a.in) + sb * a.in_ss + pc * a.in_cs + inner;
+    const cpx<R>* __restrict__ in = static_cast<const cpx<R>*>(a.in) + sb * a.in_ss + pc * a.in_cs + col_in_off(a, inner);
     cpx<R>* __restrict__ out = static_cast<cpx<R>*>(a.out) + sb * a.out_ss + pc * a.out_cs + inner;
+    const long long irs = col_in_rs(a);
 
     // the column loads are issued before the twiddle tables are built, so
     // that both latencies overlap
@@ -86,7 +95,7 @@ __global__ void __launch_bounds__(P::G* T, W) k_colfft(ColArgs a)
         const int n = P::in_pos(g, i);
         int r = n;
         if constexpr (MODE == COL_INV_PAD) r = compact_of(n, N, KC, MC);
-        v[i] = (valid && r >= 0) ? in[r * a.S] : cpx<R>{0, 0};
+        v[i] = (valid && r >= 0) ? in[r * irs] : cpx<R>{0, 0};
     }
     P::template load_tw<R>(twl, static_cast<const cpx<R>*>(a.tw));
     {
@@ -131,7 +140,7 @@ __global__ void __launch_bounds__(P::G* T, W) k_colfft_p(ColArgs a)
         valid = q < a.Q;
         const long long outer = valid ? q / a.S : 0, inner = valid ? q % a.S : 0;
         const long long sb = outer / a.nc, pc = outer % a.nc;
-        off_in = sb * a.in_ss + pc * a.in_cs + inner;
+        off_in = sb * a.in_ss + pc * a.in_cs + col_in_off(a, inner);
         off_out = sb * a.out_ss + pc * a.out_cs + inner;
     };
     auto load = [&](long long tile, cpx<R>(&v)[E]) {
@@ -144,7 +153,7 @@ __global__ void __launch_bounds__(P::G* T, W) k_colfft_p(ColArgs a)
             const int n = P::in_pos(g, i);
             int r = n;
             if constexpr (MODE == COL_INV_PAD) r = compact_of(n, N, KC, MC);
-            v[i] = (valid && r >= 0) ? in[r * a.S] : cpx<R>{0, 0};
+            v[i] = (valid && r >= 0) ? in[r * col_in_rs(a)] : cpx<R>{0, 0};
         }
     };
     cpx<R> v[E], vn[E];
@@ -534,12 +543,14 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
         long long samp;
         int s;
     };
+    constexpr int CB = compact_cb(sizeof(cpx<R>));
+    const long long cols = compact_cols(a.MMx, sizeof(cpx<R>));  // padded columns per sample
     auto column = [&](long long tile) {
         const long long q = tile * T + c;
         Col k;
-        k.valid = q < a.Q;
-        k.samp = k.valid ? q / a.MMx : 0;
-        k.s = k.valid ? (int)(q % a.MMx) : 0;
+        k.valid = q < a.Q && q % cols < a.MMx;
+        k.samp = k.valid ? q / cols : 0;
+        k.s = k.valid ? (int)(q % cols) : 0;
         return k;
     };
     auto load = [&](int p, cpx<R>(&v)[E], int gg, const Col& k) {
@@ -666,7 +677,10 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
             }
         }
     };
-    auto st_of = [&](int jz) { return samp * a.st_ss + (long long)jz * a.MMx + s; };
+    // compact offset of row jz of component 0 (components are st_cs apart)
+    auto st_of = [&](int jz) {
+        return samp * a.st_ss + (long long)((unsigned)s / CB) * 3 * a.st_cs + (long long)jz * CB + (unsigned)s % CB;
+    };
     auto k2_of = [&](int kzi) { return kxi * kxi + kyi * kyi + kzi * kzi; };
 
     if constexpr (MODE == F3_PROJ) {

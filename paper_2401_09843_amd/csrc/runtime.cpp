@@ -65,7 +65,9 @@ struct Group {
     std::vector<int> samples;  // context sample index of batch slot b
     const SizeKernels* kern = nullptr;
     long long MMx = 0;         // M * Mx, columns of a compact plane
-    long long st = 0;          // compact state elements per sample, 3 M M Mx
+    long long MMxp = 0;        // MMx rounded up to the compact column block
+    long long st = 0;          // compact state elements per sample, 3 M MMxp
+    int eb = 8;                // bytes per complex element
     double eps = 0, m_cut = 0;
     void *U0 = nullptr, *U1 = nullptr;  // compact states
     void *A = nullptr, *Bw = nullptr, *C = nullptr;  // pass workspaces
@@ -229,14 +231,33 @@ ns_status upload(ns_ctx* c, void* dst, const void* src, size_t bytes)
     return NS_OK;
 }
 
-ns_status setup_group(ns_ctx* c, Group& g)
+// cutoff and compact-layout sizes of a group of grid size g.N
+void set_dims(Group& g, bool f64)
 {
-    const int N = g.N;
-    g.K = (N - 1) / 3;
+    g.K = (g.N - 1) / 3;
     g.M = 2 * g.K + 1;
     g.Mx = g.K + 1;
     g.MMx = (long long)g.M * g.Mx;
-    g.st = 3LL * g.M * g.MMx;
+    g.eb = f64 ? 16 : 8;
+    g.MMxp = compact_cols(g.MMx, g.eb);
+    g.st = 3LL * g.M * g.MMxp;
+}
+
+// column-pass input fields for a compact array of nc components per sample
+void compact_in(ColArgs& a, const Group& g, int nc)
+{
+    const int cb = compact_cb(g.eb);
+    a.in_cs = (long long)g.M * cb;
+    a.in_ss = (long long)nc * g.M * g.MMxp;
+    a.in_bs = (long long)nc * g.M * cb;
+    a.in_rs = cb;
+    a.in_cbl = compact_cbl(g.eb);
+}
+
+ns_status setup_group(ns_ctx* c, Group& g)
+{
+    const int N = g.N;
+    set_dims(g, c->f64);
     g.B = (int)g.samples.size();
     g.kern = find_kernels(N, c->f64);
     if (!g.kern) return fail(c, NS_ERR_UNSUPPORTED, "grid size N=%d is not supported", N);
@@ -326,8 +347,9 @@ PassArgs pass_args(const Group& g, const void* us, void* out, const void* u0, do
 {
     const long long N = g.N, B = g.B, M = g.M, Mx = g.Mx, MMx = g.MMx;
     PassArgs a;
-    // I1: [B][3][M][MMx] -> [B][3 of 6][N][MMx]
-    a.i1 = ColArgs{us, g.A, g.tw, B * 3 * MMx, MMx, 3, M * MMx, 3 * M * MMx, N * MMx, 6 * N * MMx, g.K, g.M, 1.0};
+    // I1: compact [B][3] -> [B][3 of 6][N][MMx]
+    a.i1 = ColArgs{us, g.A, g.tw, B * 3 * MMx, MMx, 3, 0, 0, N * MMx, 6 * N * MMx, g.K, g.M, 1.0};
+    compact_in(a.i1, g, 3);
     // I2: [B][3 of 6][N][M][Mx] -> [B*3*N][N][Mx]
     a.i2 = ColArgs{g.A, g.Bw, g.tw, B * 3 * N * Mx, Mx, 3 * N, M * Mx, 6 * N * M * Mx, N * Mx, 3 * N * N * Mx,
                    g.K, g.M, 1.0};
@@ -336,10 +358,10 @@ PassArgs pass_args(const Group& g, const void* us, void* out, const void* u0, do
     // F2: [B*6*N][N][Mx] -> [B*6*N][M][Mx]
     a.f2 = ColArgs{g.C, g.A, g.tw, B * 6 * N * Mx, Mx, 6 * N, N * Mx, 6 * N * N * Mx, M * Mx, 6 * N * M * Mx,
                    g.K, g.M, 1.0 / N};
-    // F3: [B][6][N][MMx] -> compact [B][3][M][MMx]
+    // F3: [B][6][N][MMx] -> compact [B][3]
     // (the fused form also writes I1 of `out` over its input: [B][3 of 6][N][MMx])
-    a.f3 = F3Args{g.A, u0, us, out, g.tw, g.rate, dt, B * MMx, (int)MMx, g.Mx, g.K, g.M,
-                  6 * N * MMx, N * MMx, g.st, M * MMx, ca, cb, cc, 1.0 / N, nullptr, nullptr, 0.0, 0.0, g.A};
+    a.f3 = F3Args{g.A, u0, us, out, g.tw, g.rate, dt, B * g.MMxp, (int)MMx, g.Mx, g.K, g.M,
+                  6 * N * MMx, N * MMx, g.st, M * compact_cb(g.eb), ca, cb, cc, 1.0 / N, nullptr, nullptr, 0.0, 0.0, g.A};
     return a;
 }
 
@@ -494,11 +516,13 @@ ns_status run_vjp(ns_ctx* c, Group& g, const void* u, const void* lam, void* out
     HIP_TRY(c, launch_strain(c->f64, lam, g.Sb, g.K, B, s));
     // the column passes use the schedules chosen for the forward I1, I2, F2
     const auto zinv = k->inv[g.sel[0]].fn, yinv = k->inv[g.sel[1]].fn, yfwd = k->fwd[g.sel[3]].fn;
-    // z: strain [B][6][M][MMx] and velocity [B][3][M][MMx] -> [B][9][N][MMx]
-    ColArgs s1{g.Sb, g.A9, g.tw, B * 6 * MMx, MMx, 6, M * MMx, 6 * M * MMx, N * MMx, 9 * N * MMx, g.K, g.M, 1.0};
+    // z: compact strain [B][6] and velocity [B][3] -> [B][9][N][MMx]
+    ColArgs s1{g.Sb, g.A9, g.tw, B * 6 * MMx, MMx, 6, 0, 0, N * MMx, 9 * N * MMx, g.K, g.M, 1.0};
+    compact_in(s1, g, 6);
     HIP_TRY(c, zinv(s1, s));
-    ColArgs u1{u, (char*)g.A9 + cw * 6 * N * MMx, g.tw, B * 3 * MMx, MMx, 3, M * MMx, 3 * M * MMx, N * MMx,
-               9 * N * MMx, g.K, g.M, 1.0};
+    ColArgs u1{u, (char*)g.A9 + cw * 6 * N * MMx, g.tw, B * 3 * MMx, MMx, 3, 0, 0, N * MMx, 9 * N * MMx, g.K, g.M,
+               1.0};
+    compact_in(u1, g, 3);
     HIP_TRY(c, zinv(u1, s));
     // y: [B][9N][M][Mx] -> [B][9N][N][Mx]
     ColArgs y1{g.A9, g.B9, g.tw, B * 9 * N * Mx, Mx, 9 * N, M * Mx, 9 * N * M * Mx, N * Mx, 9 * N * N * Mx,
@@ -512,8 +536,8 @@ ns_status run_vjp(ns_ctx* c, Group& g, const void* u, const void* lam, void* out
                g.K, g.M, 1.0 / N};
     HIP_TRY(c, yfwd(y2, s));
     // z forward + adjoint stage epilogue
-    F3Args f{g.A, g.L3, lam, out, g.tw, g.rate, dt, B * MMx, (int)MMx, g.Mx, g.K, g.M,
-             3 * N * MMx, N * MMx, g.st, M * MMx, c3, 0.0, cc, 1.0 / N, g.L2, g.L1, c2, c1};
+    F3Args f{g.A, g.L3, lam, out, g.tw, g.rate, dt, B * g.MMxp, (int)MMx, g.Mx, g.K, g.M,
+             3 * N * MMx, N * MMx, g.st, M * compact_cb(g.eb), c3, 0.0, cc, 1.0 / N, g.L2, g.L1, c2, c1};
     HIP_TRY(c, k->f3_adj(f, s));
     return NS_OK;
 }
@@ -1197,9 +1221,9 @@ ns_status ns_forward(ns_ctx* c, const void* const* u, void* const* uh)
         ColArgs a{g.C, g.A, g.tw, 3 * N * Mx, Mx, 3 * N, N * Mx, 3 * N * N * Mx, M * Mx, 3 * N * M * Mx,
                   g.K, g.M, 1.0 / N};
         HIP_TRY(c, g.kern->fwd[g.sel[3]].fn(a, s));
-        // z + T + Leray: [3][N][MMx] -> compact [3][M][MMx]
-        F3Args f{g.A, nullptr, nullptr, g.U1, g.tw, g.rate, g.ones, MMx, (int)MMx, g.Mx, g.K, g.M,
-                 0, N * MMx, 0, M * MMx, 0.0, 0.0, 0.0, 1.0 / N, nullptr, nullptr, 0.0, 0.0};
+        // z + T + Leray: [3][N][MMx] -> compact [3]
+        F3Args f{g.A, nullptr, nullptr, g.U1, g.tw, g.rate, g.ones, g.MMxp, (int)MMx, g.Mx, g.K, g.M,
+                 0, N * MMx, 0, M * compact_cb(g.eb), 0.0, 0.0, 0.0, 1.0 / N, nullptr, nullptr, 0.0, 0.0};
         HIP_TRY(c, g.kern->f3_proj(f, s));
         HIP_TRY(c, launch_unpack(c->f64, g.U1, uh[i], g.L, g.K, s));
     }
@@ -1213,7 +1237,8 @@ static ns_status inverse_one(ns_ctx* c, Group& g, const void* uh, void* u)
     const long long N = g.N, M = g.M, Mx = g.Mx, MMx = g.MMx;
     hipStream_t s = c->stream;
     HIP_TRY(c, launch_pack(c->f64, uh, g.U1, g.L, g.K, s));
-    ColArgs a1{g.U1, g.A, g.tw, 3 * MMx, MMx, 3, M * MMx, 3 * M * MMx, N * MMx, 3 * N * MMx, g.K, g.M, 1.0};
+    ColArgs a1{g.U1, g.A, g.tw, 3 * MMx, MMx, 3, 0, 0, N * MMx, 3 * N * MMx, g.K, g.M, 1.0};
+    compact_in(a1, g, 3);
     HIP_TRY(c, g.kern->inv[g.sel[0]].fn(a1, s));
     ColArgs a2{g.A, g.Bw, g.tw, 3 * N * Mx, Mx, 3 * N, M * Mx, 3 * N * M * Mx, N * Mx, 3 * N * N * Mx,
                g.K, g.M, 1.0};
@@ -1321,8 +1346,19 @@ ns_status ns_tape_bytes(const ns_ctx* c, int32_t nsteps, size_t* per)
     return NS_OK;
 }
 
-// tape layout per sample: [step][stage u^n, u1, u2][3][M][M][Mx] compact
+// tape layout per sample: [step][stage u^n, u1, u2][compact state]
 static size_t tape_step_bytes(const ns_ctx* c, const Group& g) { return (size_t)g.st * 2 * c->rsz * 3; }
+
+ns_status ns_tape_step_bytes(const ns_ctx* c, int32_t n, size_t* bytes)
+{
+    if (!c || !bytes) return NS_ERR_ARG;
+    for (const Group& g : c->groups)
+        if (g.L == n) {
+            *bytes = tape_step_bytes(c, g);
+            return NS_OK;
+        }
+    return NS_ERR_ARG;
+}
 
 ns_status ns_step_taped(ns_ctx* c, void* const* uh, const double* dt, int32_t nsteps, void* const* tape)
 {
@@ -1503,11 +1539,7 @@ ns_status ns_rhs_noalloc(const ns_params* p, const void* uin, void* rout, void* 
     g.N = pad ? 3 * L / 2 : L;
     g.kern = find_kernels(g.N, f64);
     if (!g.kern) return noalloc_fail(NS_ERR_UNSUPPORTED, "grid size N=%d is not supported", g.N);
-    g.K = (g.N - 1) / 3;
-    g.M = 2 * g.K + 1;
-    g.Mx = g.K + 1;
-    g.MMx = (long long)g.M * g.Mx;
-    g.st = 3LL * g.M * g.MMx;
+    set_dims(g, f64);
     g.B = 1;
     g.eps = p->eps >= 0 ? p->eps : 1e-3 * std::pow(32.0 / g.L, 2.0 * p->s - 1.0);
     g.m_cut = p->m_cut >= 0 ? p->m_cut : g.L / 3.0;

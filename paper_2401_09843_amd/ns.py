@@ -25,7 +25,8 @@ NS_GRAPH_CHAIN, NS_GRAPH_BRANCHES = 64, 128
 
 # every symbol the header declares
 EXPORTS = ("ns_init", "ns_destroy", "ns_last_error", "ns_workspace_bytes", "ns_supported_sizes", "ns_forward",
-           "ns_inverse", "ns_project", "ns_rhs", "ns_step", "ns_tape_bytes", "ns_step_taped", "ns_adjoint_step", "ns_adjoint_steps",
+           "ns_inverse", "ns_project", "ns_rhs", "ns_step", "ns_tape_bytes", "ns_tape_step_bytes", "ns_step_taped",
+           "ns_adjoint_step", "ns_adjoint_steps",
            "ns_energy_spectrum", "ns_enstrophy_spectrum", "ns_moments", "ns_structure_functions",
            "ns_wasserstein1", "ns_sync", "ns_profile", "ns_profile_read",
            "ns_variant_count", "ns_set_variant", "ns_tune_report", "ns_rhs_noalloc")
@@ -70,6 +71,7 @@ def lib() -> ctypes.CDLL:
             "ns_rhs": [P, PP, PP],
             "ns_step": [P, PP, PD, I32],
             "ns_tape_bytes": [P, I32, ctypes.POINTER(S)],
+            "ns_tape_step_bytes": [P, I32, ctypes.POINTER(S)],
             "ns_step_taped": [P, PP, PD, I32, PP],
             "ns_adjoint_step": [P, PP, PP, PD, PP],
             "ns_adjoint_steps": [P, PP, I32, PD, PP],
@@ -220,11 +222,11 @@ class Solver:
         return uhat
 
     def tape_step_bytes(self, n: int) -> int:
-        """Bytes of one step of the tape of a sample of size n: three compact
-        stage states [3][M][M][K+1] of complex numbers."""
-        K = (3 * n // 2 - 1) // 3 if self.pad else (n - 1) // 3
-        cw = 8 if self.dtype == torch.float32 else 16
-        return 9 * (2 * K + 1) ** 2 * (K + 1) * cw
+        """Bytes of one step of the tape of a sample of size n (three compact
+        stage states), as the library lays it out."""
+        b = ctypes.c_size_t()
+        self._check(self._L.ns_tape_step_bytes(self._ctx, int(n), ctypes.byref(b)))
+        return int(b.value)
 
     def new_tape(self, nsteps: int):
         return [torch.empty(max(1, nsteps * self.tape_step_bytes(n)), dtype=torch.uint8, device=self.device)
