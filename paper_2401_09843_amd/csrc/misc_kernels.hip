@@ -162,7 +162,9 @@ __global__ void __launch_bounds__(SPEC_THREADS) k_spectrum(const cpx<R>* __restr
 
 // Symmetric strain of the projected adjoint (the transpose of the nonlinear
 // term): mu = P lam on each retained mode (compact layout, all samples), then
-// S_ij-hat = (i/2)(k_i mu_j + k_j mu_i) for (xx, xy, xz, yy, yz, zz).
+// S_ij-hat = (i/2)(k_i mu_j + k_j mu_i) for (xx, xy, xz, yy, yz).  mu is
+// divergence-free, so the strain is trace-free and S_zz = -S_xx - S_yy is
+// not stored (the x pass forms it in physical space).
 template <typename R>
 __global__ void k_strain(const cpx<R>* __restrict__ lam, cpx<R>* __restrict__ S, int K, long long batch)
 {
@@ -176,7 +178,7 @@ __global__ void k_strain(const cpx<R>* __restrict__ lam, cpx<R>* __restrict__ S,
     const int kxi = (int)(m % Mx), jy = (int)((m / Mx) % M), jz = (int)(m / ((long long)Mx * M));
     const int kyi = jy <= K ? jy : jy - M, kzi = jz <= K ? jz : jz - M;
     const R kv[3] = {(R)kxi, (R)kyi, (R)kzi};
-    // compact offsets: lam has 3 components per sample, S has 6
+    // compact offsets: lam has 3 components per sample, S has 5
     const cpx<R>* l = lam + b * 3 * M * cols + compact_off(EB, 3, M, 0, jz, sc);
     const long long lcs = compact_off(EB, 3, M, 1, 0, 0);
     cpx<R> mu[3] = {l[0], l[lcs], l[2 * lcs]};
@@ -190,10 +192,10 @@ __global__ void k_strain(const cpx<R>* __restrict__ lam, cpx<R>* __restrict__ S,
             mu[c].y -= kv[c] * by;
         }
     }
-    const int ti[6] = {0, 0, 0, 1, 1, 2}, tj[6] = {0, 1, 2, 1, 2, 2};
-    cpx<R>* o = S + b * 6 * M * cols + compact_off(EB, 6, M, 0, jz, sc);
-    const long long ocs = compact_off(EB, 6, M, 1, 0, 0);
-    for (int p = 0; p < 6; ++p) {
+    const int ti[5] = {0, 0, 0, 1, 1}, tj[5] = {0, 1, 2, 1, 2};
+    cpx<R>* o = S + b * 5 * M * cols + compact_off(EB, 5, M, 0, jz, sc);
+    const long long ocs = compact_off(EB, 5, M, 1, 0, 0);
+    for (int p = 0; p < 5; ++p) {
         const int i = ti[p], j = tj[p];
         const R wx = kv[i] * mu[j].x + kv[j] * mu[i].x, wy = kv[i] * mu[j].y + kv[j] * mu[i].y;
         o[p * ocs] = {(R)-0.5 * wy, (R)0.5 * wx};  // (i/2) w

@@ -340,32 +340,32 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
           body();
       }
     } else if constexpr (MODE == X_ADJ) {
-        // inputs: components 0..5 the strain S (xx, xy, xz, yy, yz, zz),
-        // 6..8 the velocity; a_i = 2 sum_j S_ij u_j, upper triangle (i, j)
-        // adds S_ij u_j to a_i and, off the diagonal, S_ij u_i to a_j
+        // inputs: components 0..4 the trace-free strain S (xx, xy, xz, yy,
+        // yz), 5..7 the velocity; a_i = 2 sum_j S_ij u_j, upper triangle
+        // (i, j) adds S_ij u_j to a_i and, off the diagonal, S_ij u_i to a_j;
+        // S_zz = -S_xx - S_yy adds -2 (S_xx + S_yy) u_z to a_z
         cpx<R> u0[E], u1[E], u2[E], a0[E], a1[E], a2[E], v[E];
-        load_inv(6, u0);
-        load_inv(7, u1);
-        load_inv(8, u2);
+        load_inv(5, u0);
+        load_inv(6, u1);
+        load_inv(7, u2);
 #pragma unroll
         for (int i = 0; i < E; ++i) a0[i] = a1[i] = a2[i] = cpx<R>{0, 0};
-        auto fma2 = [&](cpx<R>(&acc)[E], const cpx<R>(&s)[E], const cpx<R>(&w)[E]) {
+        auto fma2 = [&](cpx<R>(&acc)[E], const cpx<R>(&s)[E], const cpx<R>(&w)[E], R f) {
 #pragma unroll
             for (int i = 0; i < E; ++i) {
-                acc[i].x += (R)2 * s[i].x * w[i].x;
-                acc[i].y += (R)2 * s[i].y * w[i].y;
+                acc[i].x += f * s[i].x * w[i].x;
+                acc[i].y += f * s[i].y * w[i].y;
             }
         };
 #pragma unroll 1
-        for (int p = 0; p < 6; ++p) {
+        for (int p = 0; p < 5; ++p) {
             load_inv(p, v);
             switch (p) {
-                case 0: fma2(a0, v, u0); break;
-                case 1: fma2(a0, v, u1); fma2(a1, v, u0); break;
-                case 2: fma2(a0, v, u2); fma2(a2, v, u0); break;
-                case 3: fma2(a1, v, u1); break;
-                case 4: fma2(a1, v, u2); fma2(a2, v, u1); break;
-                default: fma2(a2, v, u2); break;
+                case 0: fma2(a0, v, u0, 2); fma2(a2, v, u2, -2); break;
+                case 1: fma2(a0, v, u1, 2); fma2(a1, v, u0, 2); break;
+                case 2: fma2(a0, v, u2, 2); fma2(a2, v, u0, 2); break;
+                case 3: fma2(a1, v, u1, 2); fma2(a2, v, u2, -2); break;
+                default: fma2(a1, v, u2, 2); fma2(a2, v, u1, 2); break;
             }
         }
         fwd_store(0, a0);

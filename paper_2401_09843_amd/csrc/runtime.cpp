@@ -76,7 +76,7 @@ struct Group {
     std::vector<double> dt_host;  // values last uploaded to dt
     // adjoint buffers (allocated on first use): stage u2, adjoint stages,
     // strain, and 9-component pass workspaces
-    void *U2 = nullptr, *L1 = nullptr, *L2 = nullptr, *L3 = nullptr, *Sb = nullptr, *A9 = nullptr, *B9 = nullptr;
+    void *U2 = nullptr, *L1 = nullptr, *L2 = nullptr, *L3 = nullptr, *Sb = nullptr, *A8 = nullptr, *B8 = nullptr;
     int sel[NS_NPASS] = {0, 0, 0, 0, 0};  // chosen schedule variant per pass
     double tune_ms[NS_NPASS][NS_MAXV] = {};  // tuner timings (ms per launch), 0 = not timed
     // stage form: SSP-RK3 stages end in the fused F3 + inverse z pass (the
@@ -495,9 +495,9 @@ ns_status ensure_adjoint_buffers(ns_ctx* c, Group& g)
     if ((st = dalloc(c, &g.L1, cw * g.st * B))) return st;
     if ((st = dalloc(c, &g.L2, cw * g.st * B))) return st;
     if ((st = dalloc(c, &g.L3, cw * g.st * B))) return st;
-    if ((st = dalloc(c, &g.Sb, cw * 2 * g.st * B))) return st;
-    if ((st = dalloc(c, &g.A9, cw * 9ULL * N * g.MMx * B))) return st;
-    if ((st = dalloc(c, &g.B9, cw * 9ULL * N * N * g.Mx * B))) return st;
+    if ((st = dalloc(c, &g.Sb, cw * 5ULL * g.M * g.MMxp * B))) return st;
+    if ((st = dalloc(c, &g.A8, cw * 8ULL * N * g.MMx * B))) return st;
+    if ((st = dalloc(c, &g.B8, cw * 8ULL * N * N * g.Mx * B))) return st;
     return NS_OK;
 }
 
@@ -516,20 +516,20 @@ ns_status run_vjp(ns_ctx* c, Group& g, const void* u, const void* lam, void* out
     HIP_TRY(c, launch_strain(c->f64, lam, g.Sb, g.K, B, s));
     // the column passes use the schedules chosen for the forward I1, I2, F2
     const auto zinv = k->inv[g.sel[0]].fn, yinv = k->inv[g.sel[1]].fn, yfwd = k->fwd[g.sel[3]].fn;
-    // z: compact strain [B][6] and velocity [B][3] -> [B][9][N][MMx]
-    ColArgs s1{g.Sb, g.A9, g.tw, B * 6 * MMx, MMx, 6, 0, 0, N * MMx, 9 * N * MMx, g.K, g.M, 1.0};
-    compact_in(s1, g, 6);
+    // z: compact strain [B][5] and velocity [B][3] -> [B][8][N][MMx]
+    ColArgs s1{g.Sb, g.A8, g.tw, B * 5 * MMx, MMx, 5, 0, 0, N * MMx, 8 * N * MMx, g.K, g.M, 1.0};
+    compact_in(s1, g, 5);
     HIP_TRY(c, zinv(s1, s));
-    ColArgs u1{u, (char*)g.A9 + cw * 6 * N * MMx, g.tw, B * 3 * MMx, MMx, 3, 0, 0, N * MMx, 9 * N * MMx, g.K, g.M,
+    ColArgs u1{u, (char*)g.A8 + cw * 5 * N * MMx, g.tw, B * 3 * MMx, MMx, 3, 0, 0, N * MMx, 8 * N * MMx, g.K, g.M,
                1.0};
     compact_in(u1, g, 3);
     HIP_TRY(c, zinv(u1, s));
-    // y: [B][9N][M][Mx] -> [B][9N][N][Mx]
-    ColArgs y1{g.A9, g.B9, g.tw, B * 9 * N * Mx, Mx, 9 * N, M * Mx, 9 * N * M * Mx, N * Mx, 9 * N * N * Mx,
+    // y: [B][8N][M][Mx] -> [B][8N][N][Mx]
+    ColArgs y1{g.A8, g.B8, g.tw, B * 8 * N * Mx, Mx, 8 * N, M * Mx, 8 * N * M * Mx, N * Mx, 8 * N * N * Mx,
                g.K, g.M, 1.0};
     HIP_TRY(c, yinv(y1, s));
     // x: a = 2 S u -> [B][3][N*N][Mx]
-    XArgs ax{g.B9, g.C, g.tw, B * N * N / 2, N * N * Mx, N * N * Mx, 9 * N * N * Mx, 3 * N * N * Mx, g.K, 1.0 / N};
+    XArgs ax{g.B8, g.C, g.tw, B * N * N / 2, N * N * Mx, N * N * Mx, 8 * N * N * Mx, 3 * N * N * Mx, g.K, 1.0 / N};
     HIP_TRY(c, k->x_adj(ax, s));
     // y forward: [B][3N][N][Mx] -> [B][3N][M][Mx]
     ColArgs y2{g.C, g.A, g.tw, B * 3 * N * Mx, Mx, 3 * N, N * Mx, 3 * N * N * Mx, M * Mx, 3 * N * M * Mx,

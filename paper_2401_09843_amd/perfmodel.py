@@ -56,6 +56,34 @@ def step_bytes(n: int, real_bytes: int, fused: bool = False, steps_per_call: int
     return cw * (per + s1["I1_inv_z"] / steps_per_call)
 
 
+def vjp_cw(n: int, stage: int) -> dict:
+    """Complex words moved by one vector-Jacobian product of the right-hand
+    side fused with adjoint RK3 stage `stage` (1: lambda_2, 2: lambda_1,
+    3: lambda_n), one sample: the strain of P lam (five stored components of
+    the trace-free strain), inverse z and y passes of those five and of the
+    three velocity components, the x pass forming 2 S u, forward y and z
+    passes of its three components, and the stage epilogue, which reads lam
+    and the earlier adjoint stages with nonzero coefficients (two arrays in
+    stages 1 and 2, three in stage 3) and writes one."""
+    K, M, Mx = dims(n)
+    st = M * M * Mx
+    reads = 3 if stage == 3 else 2
+    return {
+        "strain": 3 * st + 5 * st,
+        "I1_inv_z": 8 * st + 8 * n * M * Mx,
+        "I2_inv_y": 8 * n * M * Mx + 8 * n * n * Mx,
+        "X_adj": 8 * n * n * Mx + 3 * n * n * Mx,
+        "F2_fwd_y": 3 * n * n * Mx + 3 * n * M * Mx,
+        "F3_adj": 3 * n * M * Mx + 3 * reads * st + 3 * st,
+    }
+
+
+def adjoint_step_bytes(n: int, real_bytes: int) -> float:
+    """Algorithmic HBM bytes of one adjoint SSP-RK3 step (three VJPs) of one
+    sample, reading its stage states from a tape."""
+    return 2 * real_bytes * sum(sum(vjp_cw(n, s).values()) for s in (1, 2, 3))
+
+
 # ---- the paper's lower bounds (Sec. 5.1, eqs. (5.1)-(5.3)), N grid, p ranks,
 # s bytes per scalar, bandwidths in bytes/s
 def t_pad(N, p, s, beta):

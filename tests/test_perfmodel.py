@@ -63,3 +63,19 @@ def test_fused_model():
     assert pm.step_bytes(n, 4, fused=True, steps_per_call=1) == pytest.approx(base - cw * 3 * 225 + cw * 585)
     bpl = pm.pass_bytes_per_launch(n, 4, fused=True)
     assert bpl["F3_fwd_z_epilogue"] == pytest.approx(pm.pass_bytes_per_launch(n, 4)["F3_fwd_z_epilogue"] + cw * 360)
+
+
+def test_adjoint_step_bytes_against_a_forward_step():
+    """An adjoint step (three VJPs from a tape) moves about 1.4 times the
+    bytes of a forward step: each VJP inverse-transforms eight fields (five
+    strain components and three velocity components) where a right-hand
+    side inverse-transforms three and forward-transforms six."""
+    from paper_2401_09843_amd import perfmodel
+
+    for n in (32, 128, 1024):
+        r = perfmodel.adjoint_step_bytes(n, 8) / perfmodel.step_bytes(n, 8)
+        assert 1.3 < r < 1.45, (n, r)
+        K, M, Mx = perfmodel.dims(n)
+        v = perfmodel.vjp_cw(n, 3)
+        assert v["strain"] == 8 * M * M * Mx
+        assert v["X_adj"] == 11 * n * n * Mx
