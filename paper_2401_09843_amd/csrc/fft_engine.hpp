@@ -395,6 +395,45 @@ struct Stages<N, G, DIR, PD, LS, SP, WS, DB, T, P, OFF, R, Rest...> {
         else lds_sync<WS>();
     }
 
+    // The exchange before a last radix-2 stage, for a line of G = 16 lanes
+    // that form one DPP row (consecutive threads, LS = 1), when this stage
+    // has one butterfly per thread (E = R) and span P = G / 2.  Thread t then
+    // holds x[h N/2 + t % (G/2) + m G/2], h = t / (G/2), and butterfly q of
+    // the last stage in thread t takes x[t + q G] and x[t + q G + N/2]: slot
+    // 2q + h of its own lane and of lane t ^ (G/2).  So each butterfly needs
+    // one value from the partner lane, which a row rotation by 8 brings over
+    // in registers: no LDS and no barrier.
+    template <int R2>
+    static constexpr bool lane_swap()
+    {
+        return R2 == 2 && sizeof...(Rest) == 1 && G == 16 && LS == 1 && NB == 1 && P == G / 2 && DB == 0;
+    }
+    __device__ __forceinline__ static T row_ror8(T x)
+    {
+        // DPP control 0x128: row_ror:8 (lane l of a 16-lane row reads lane (l + 8) mod 16)
+        if constexpr (sizeof(T) == 4) {
+            return __builtin_bit_cast(T, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x128, 0xF, 0xF, false));
+        } else {
+            const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+            const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, 0x128, 0xF, 0xF, false);
+            const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), 0x128, 0xF, 0xF, false);
+            return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+        }
+    }
+    __device__ __forceinline__ static void swap_exchange(cpx<T> (&v)[E], int t)
+    {
+        const bool h = (t & (G / 2)) != 0;
+#pragma unroll
+        for (int q = 0; q < E / 2; ++q) {
+            // element-wise selects (a conditional store into v would be
+            // turned into a dynamically indexed stack array)
+            const cpx<T> a0 = v[2 * q], a1 = v[2 * q + 1];
+            const T rx = row_ror8(h ? a0.x : a1.x), ry = row_ror8(h ? a0.y : a1.y);
+            v[2 * q] = {h ? rx : a0.x, h ? ry : a0.y};
+            v[2 * q + 1] = {h ? a1.x : rx, h ? a1.y : ry};
+        }
+    }
+
     template <typename L>
     __device__ __forceinline__ static void run(cpx<T> (&v)[E], int t, L* lds, const cpx<T>* __restrict__ tw, int dbo,
                                                int& par)
@@ -411,7 +450,9 @@ struct Stages<N, G, DIR, PD, LS, SP, WS, DB, T, P, OFF, R, Rest...> {
         }
         if constexpr (sizeof...(Rest) > 0) {
             constexpr int R2 = Radices<Rest...>::first;
-            if constexpr (SP == 0) {
+            if constexpr (lane_swap<R2>()) {
+                swap_exchange(v, t);
+            } else if constexpr (SP == 0) {
                 exchange<R2>(v, t, lds, [](cpx<T> a) { return a; }, [](cpx<T>& d, cpx<T> a) { d = a; }, dbo, par);
             } else {
                 T* l = reinterpret_cast<T*>(lds);
