@@ -326,7 +326,7 @@ def ensemble_record(args, steps, warmup, batched_only=False, statistics=False):
     fields, dts = ensemble_fields(args.family, dev)
     log("ensemble: %d samples, %d steps" % (len(ENS_SIZES), steps))
     E = ns.Solver(ENS_SIZES, dtype=torch.float32, graph=True, tune=not args.no_tune, tune_cache=args.tune_cache,
-                  fuse=fuse_arg(args))
+                  fuse=fuse_arg(args), graph_form=args.graph_form)
     uhs = E.forward(fields)
     del fields
     init = [t.clone() for t in uhs]
@@ -510,6 +510,9 @@ def main():
                     help="Algorithm 2 in its padded form: --n modes per axis, passes on the 3n/2 grid")
     ap.add_argument("--print-source-hash", action="store_true")
     ap.add_argument("--ensemble", action="store_true", help="run the 96-sample ensemble workload alone")
+    ap.add_argument("--graph-form", default=None, choices=["chain", "branches"],
+                    help="ensemble: launch the size groups of the captured step as one chain or as concurrent "
+                         "graph branches (default: the autotuner's choice)")
     ap.add_argument("--batched-only", action="store_true",
                     help="with --ensemble: time the batched steps only (no looped solvers, no statistics)")
     ap.add_argument("--family", default="shear", choices=["shear", "tg", "cyl"],
