@@ -1,0 +1,63 @@
+"""Host check of the register exchange the FFT engine does by a DPP row
+rotation: for a line of G = 16 threads held in one 16-lane row, when the
+second-to-last stage has one butterfly per thread (E = R) and span P = G/2
+and the last stage is radix 2, every value a thread needs for its last-stage
+butterflies is either in its own registers or in lane t ^ 8 (slot 2q + h,
+h = t / 8).  The index maps are the Stockham ones of the engine: a stage of
+span P and radix R writes output m of butterfly b to (b - k) R + k + m P,
+k = b mod P, and the next stage of radix R2 reads t + q G + m N / R2."""
+import itertools
+
+import pytest
+
+
+def holdings(N, G, radices):
+    """Position -> (thread, slot) after all stages but the last."""
+    E = N // G
+    assert all(E % R == 0 for R in radices), "each radix must divide the elements per thread"
+    P = 1
+    pos = {}
+    for s, R in enumerate(radices[:-1]):
+        NB = N // (R * G)
+        pos = {}
+        for t in range(G):
+            for q in range(NB):
+                b = t + q * G
+                k = b % P
+                for m in range(R):
+                    pos[(b - k) * R + k + m * P] = (t, q * R + m)
+        P *= R
+    assert sorted(pos) == list(range(N))
+    return pos, P, E
+
+
+@pytest.mark.parametrize("N, radices", [(128, (8, 8, 2)), (256, (8, 16, 2))])
+def test_last_radix2_exchange_is_a_lane_swap(N, radices):
+    G = 16
+    pos, P, E = holdings(N, G, radices)
+    R = radices[-2]
+    if not (N // (R * G) == 1 and P // R == G // 2):
+        pytest.skip("the engine takes the LDS exchange for this plan")
+    for t in range(G):
+        h = t // (G // 2)
+        for q in range(E // 2):
+            b = t + q * G
+            for m, p in enumerate((b, b + N // 2)):
+                src_t, src_slot = pos[p]
+                assert src_slot == 2 * q + h
+                own = (m == 0 and h == 0) or (m == 1 and h == 1)
+                assert src_t == (t if own else t ^ (G // 2)), (t, q, m)
+
+
+@pytest.mark.parametrize("N, radices", [(256, (16, 8, 2)), (256, (8, 4, 4, 2))])
+def test_wider_spans_keep_the_values_in_their_lane(N, radices):
+    """With the second-to-last span P >= G (several butterflies per thread)
+    every value of a thread's last-stage butterflies is already its own: the
+    swap is needed only for P = G / 2."""
+    G = 16
+    pos, P, E = holdings(N, G, radices)
+    assert P // radices[-2] >= G
+    for t, q in itertools.product(range(G), range(E // 2)):
+        b = t + q * G
+        for p in (b, b + N // 2):
+            assert pos[p][0] == t
