@@ -29,7 +29,7 @@ SizeKernels make32()
     add_f3<PB, 8, 0, 1, R>(k, "G16 r8.8.2 T8");
     add_f3<PA, 16, 0, 1, R>(k, "G8 r16.8 T16");
     add_f3<PC, 8, 0, 1, R>(k, "G32 r4.4.4.2 T8");
-    // the adjoint x pass holds nine fields per thread: four elements each
+    // the adjoint x pass holds eight fields per thread: four elements each
     k.x_adj = launch_x<PC, PCR, 4, X_ADJ, 1, R>;
     return k;
 }
@@ -43,7 +43,7 @@ SizeKernels make64()
     add_x<PC, PCR, 4, 1, R>(k, "G32 r4.4.4.2 U4");
     add_f3<PB, 4, 0, 1, R>(k, "G16 r8.8.2 T4");
     add_f3<PC, 4, 0, 1, R>(k, "G32 r4.4.4.2 T4");
-    // the adjoint x pass holds nine fields per thread: four elements each
+    // the adjoint x pass holds eight fields per thread: four elements each
     k.x_adj = launch_x<PC, PCR, 4, X_ADJ, 1, R>;
     return k;
 }
