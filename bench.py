@@ -127,16 +127,17 @@ def fuse_arg(args):
     return True if args.fuse else (False if args.no_fuse else None)
 
 
-def kernel_source_hash() -> str:
-    """SHA-256 of the device-code sources (the kernels, their launchers and
-    the per-size schedules; not the host runtime); PMC traffic figures are
-    valid only for the kernels they were measured on."""
+def kernel_source_hash(n: int = 1024) -> str:
+    """SHA-256 of the device-code sources the pass kernels of grid size n are
+    built from (the shared kernel headers and size_<n>.hip; not the host
+    runtime); PMC traffic figures are valid only for the kernels they were
+    measured on."""
     import glob
     import hashlib
 
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2401_09843_amd", "csrc")
-    for p in sorted(glob.glob(os.path.join(csrc, "*.hpp")) + glob.glob(os.path.join(csrc, "*.hip"))):
+    for p in sorted(glob.glob(os.path.join(csrc, "*.hpp")) + [os.path.join(csrc, "size_%d.hip" % n)]):
         with open(p, "rb") as f:
             h.update(os.path.basename(p).encode())
             h.update(f.read())
@@ -154,7 +155,7 @@ def measured_traffic(kernel: str, n: int, variant: str, stage_form: str):
         return None
     with open(path) as f:
         d = json.load(f)
-    if (d.get("source_hash") != kernel_source_hash() or d.get("variant") != variant
+    if (d.get("source_hash") != kernel_source_hash(n) or d.get("variant") != variant
             or d.get("stage_form") != stage_form):
         return None
     return d.get("bytes_per_launch")
