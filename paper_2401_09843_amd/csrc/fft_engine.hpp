@@ -395,28 +395,35 @@ struct Stages<N, G, DIR, PD, LS, SP, WS, DB, T, P, OFF, R, Rest...> {
         else lds_sync<WS>();
     }
 
-    // The exchange before a last radix-2 stage, for a line of G = 16 lanes
-    // that form one DPP row (consecutive threads, LS = 1), when this stage
-    // has one butterfly per thread (E = R) and span P = G / 2.  Thread t then
-    // holds x[h N/2 + t % (G/2) + m G/2], h = t / (G/2), and butterfly q of
-    // the last stage in thread t takes x[t + q G] and x[t + q G + N/2]: slot
+    // The exchange before a last radix-2 stage, for a line of G = 16 or 32
+    // consecutive lanes (LS = 1), when this stage has one butterfly per
+    // thread (E = R) and span P = G / 2.  Thread t then holds
+    // x[h N/2 + t % (G/2) + m G/2], h = t / (G/2), and butterfly q of the
+    // last stage in thread t takes x[t + q G] and x[t + q G + N/2]: slot
     // 2q + h of its own lane and of lane t ^ (G/2).  So each butterfly needs
-    // one value from the partner lane, which a row rotation by 8 brings over
-    // in registers: no LDS and no barrier.
+    // one value from the partner lane, which a cross-lane move brings over in
+    // registers (G = 16: a DPP row rotation by 8; G = 32: ds_swizzle with
+    // xor mask 16, which goes through the LDS crossbar but not LDS memory):
+    // no LDS buffer and no barrier.
     template <int R2>
     static constexpr bool lane_swap()
     {
-        return R2 == 2 && sizeof...(Rest) == 1 && G == 16 && LS == 1 && NB == 1 && P == G / 2 && DB == 0;
+        return R2 == 2 && sizeof...(Rest) == 1 && (G == 16 || G == 32) && LS == 1 && NB == 1 && P == G / 2 &&
+               DB == 0;
     }
-    __device__ __forceinline__ static T row_ror8(T x)
+    __device__ __forceinline__ static int swap_word(int w)
     {
-        // DPP control 0x128: row_ror:8 (lane l of a 16-lane row reads lane (l + 8) mod 16)
+        if constexpr (G == 16) return __builtin_amdgcn_mov_dpp(w, 0x128, 0xF, 0xF, false);  // row_ror:8
+        else return __builtin_amdgcn_ds_swizzle(w, 0x401F);  // bit mode: and 0x1F, or 0, xor 0x10
+    }
+    __device__ __forceinline__ static T partner(T x)
+    {
         if constexpr (sizeof(T) == 4) {
-            return __builtin_bit_cast(T, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x128, 0xF, 0xF, false));
+            return __builtin_bit_cast(T, swap_word(__builtin_bit_cast(int, x)));
         } else {
             const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
-            const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, 0x128, 0xF, 0xF, false);
-            const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), 0x128, 0xF, 0xF, false);
+            const unsigned lo = (unsigned)swap_word((int)(unsigned)u);
+            const unsigned hi = (unsigned)swap_word((int)(unsigned)(u >> 32));
             return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
         }
     }
@@ -428,7 +435,7 @@ struct Stages<N, G, DIR, PD, LS, SP, WS, DB, T, P, OFF, R, Rest...> {
             // element-wise selects (a conditional store into v would be
             // turned into a dynamically indexed stack array)
             const cpx<T> a0 = v[2 * q], a1 = v[2 * q + 1];
-            const T rx = row_ror8(h ? a0.x : a1.x), ry = row_ror8(h ? a0.y : a1.y);
+            const T rx = partner(h ? a0.x : a1.x), ry = partner(h ? a0.y : a1.y);
             v[2 * q] = {h ? rx : a0.x, h ? ry : a0.y};
             v[2 * q + 1] = {h ? a1.x : rx, h ? a1.y : ry};
         }
