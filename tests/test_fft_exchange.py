@@ -1,9 +1,9 @@
-"""Host check of the register exchange the FFT engine does by a DPP row
-rotation: for a line of G = 16 threads held in one 16-lane row, when the
+"""Host check of the register exchange the FFT engine does by cross-lane
+moves (a DPP row rotation for 16-thread lines, ds_swizzle for 32): when the
 second-to-last stage has one butterfly per thread (E = R) and span P = G/2
 and the last stage is radix 2, every value a thread needs for its last-stage
-butterflies is either in its own registers or in lane t ^ 8 (slot 2q + h,
-h = t / 8).  The index maps are the Stockham ones of the engine: a stage of
+butterflies is either in its own registers or in lane t ^ (G/2) (slot
+2q + h, h = t / (G/2)).  The index maps are the Stockham ones of the engine: a stage of
 span P and radix R writes output m of butterfly b to (b - k) R + k + m P,
 k = b mod P, and the next stage of radix R2 reads t + q G + m N / R2."""
 import itertools
@@ -31,9 +31,8 @@ def holdings(N, G, radices):
     return pos, P, E
 
 
-@pytest.mark.parametrize("N, radices", [(128, (8, 8, 2)), (256, (8, 16, 2))])
-def test_last_radix2_exchange_is_a_lane_swap(N, radices):
-    G = 16
+@pytest.mark.parametrize("N, G, radices", [(128, 16, (8, 8, 2)), (256, 16, (8, 16, 2)), (128, 32, (4, 4, 4, 2))])
+def test_last_radix2_exchange_is_a_lane_swap(N, G, radices):
     pos, P, E = holdings(N, G, radices)
     R = radices[-2]
     if not (N // (R * G) == 1 and P // R == G // 2):
