@@ -429,6 +429,54 @@ def ensemble_record(args, steps, warmup, batched_only=False, statistics=False):
     return rec, E, uhs
 
 
+def adjoint_record(args, steps, warmup):
+    """Discrete adjoint at 128^3 FP64 (the adjoint workload): the seed-0 shear
+    layer, CFL dt, graph-replayed plain steps, taped steps (the stage states
+    recorded) and adjoint steps back through that tape, each timed over
+    `steps` steps after `warmup`; the adjoint step's cost over a plain step
+    against the byte model's 1.38."""
+    import torch
+
+    from paper_2401_09843_amd import inputs, ns, perfmodel
+
+    n = 128
+    dev = torch.device("cuda", 0)
+    u, _, _ = inputs.shear_layer_torch(n, seed=0, device=dev, dtype=torch.float64)
+    dt = float(0.5 * (2 * math.pi / n) / u.abs().sum(0).max().item())
+    S = ns.Solver(n, dtype=torch.float64, graph=True, tune=not args.no_tune, tune_cache=args.tune_cache)
+    uh0 = S.forward(u)
+    del u
+
+    def timed(fn):
+        fn(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn(steps)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3
+
+    x = uh0.clone()
+    t_plain = timed(lambda k: S.step(x, dt, k))
+    tape = S.new_tape(max(steps, warmup))
+    x = uh0.clone()
+    t_taped = timed(lambda k: S.step_taped(x, dt, k, tape))
+    lam = uh0.clone()
+    t_adj = timed(lambda k: S.adjoint_steps(lam, dt, tape, k))
+    ok = bool(torch.isfinite(torch.view_as_real(lam)).all().item())
+    fb, ab = perfmodel.step_bytes(n, 8), perfmodel.adjoint_step_bytes(n, 8)
+    S.close()
+    return {
+        "workload": "discrete adjoint, shear layer 128^3 FP64, CFL 0.5",
+        "steps": steps, "warmup": warmup,
+        "plain_ms_per_step": t_plain, "taped_ms_per_step": t_taped, "adjoint_ms_per_step": t_adj,
+        "adjoint_over_plain": t_adj / t_plain,
+        "adjoint_over_plain_bytes_model": ab / fb,
+        "adjoint_step_roofline_frac": ab / (t_adj * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "plain_step_roofline_frac": fb / (t_plain * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "finite": ok,
+    }
+
+
 def ensemble_statistics(E, uhs):
     """In-situ statistics of the final ensemble: mean energy and enstrophy
     spectra, pointwise mean / variance over the 64 samples at 128^3,
@@ -511,6 +559,8 @@ def main():
                     help="Algorithm 2 in its padded form: --n modes per axis, passes on the 3n/2 grid")
     ap.add_argument("--print-source-hash", action="store_true")
     ap.add_argument("--ensemble", action="store_true", help="run the 96-sample ensemble workload alone")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time plain, taped and adjoint steps at 128^3 FP64 (the adjoint workload) alone")
     ap.add_argument("--graph-form", default=None, choices=["chain", "branches"],
                     help="ensemble: launch the size groups of the captured step as one chain or as concurrent "
                          "graph branches (default: the autotuner's choice)")
@@ -545,6 +595,10 @@ def main():
         args.steps = 200 if args.ensemble else 20
     if args.ensemble:
         run_ensemble(args)
+        return
+    if args.adjoint:
+        torch.cuda.set_device(torch.device("cuda", 0))
+        print(json.dumps(adjoint_record(args, args.steps, args.warmup)))
         return
 
     torch.cuda.set_device(torch.device("cuda", 0))

@@ -191,6 +191,15 @@ constexpr int x_line_len()
     return a > b ? a : b;
 }
 
+// The adjoint x pass parks its three transformed velocity fields in LDS
+// (3 N complex values per pair of lines) when that takes at most 32 KiB per
+// block, instead of holding them in registers next to the accumulators.
+template <class PI, class PF, int U, typename R>
+constexpr bool xadj_park()
+{
+    return 3 * PI::N * U * sizeof(cpx<R>) <= 32768;
+}
+
 // Two real lines l1 = 2u, l2 = 2u+1 share one complex transform: for a C2R,
 // Z = A + iB with A, B the Hermitian half spectra gives z = a + i b; for an
 // R2C, Z = FFT(a + i b) splits as A_k = (Z_k + conj Z_{N-k})/2,
@@ -343,29 +352,49 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
         // inputs: components 0..4 the trace-free strain S (xx, xy, xz, yy,
         // yz), 5..7 the velocity; a_i = 2 sum_j S_ij u_j, upper triangle
         // (i, j) adds S_ij u_j to a_i and, off the diagonal, S_ij u_i to a_j;
-        // S_zz = -S_xx - S_yy adds -2 (S_xx + S_yy) u_z to a_z
-        cpx<R> u0[E], u1[E], u2[E], a0[E], a1[E], a2[E], v[E];
-        load_inv(5, u0);
-        load_inv(6, u1);
-        load_inv(7, u2);
+        // S_zz = -S_xx - S_yy adds -2 (S_xx + S_yy) u_z to a_z.
+        // With xadj_park: the transformed velocities wait in this line pair's
+        // slice of LDS instead of registers; every thread reads back only the
+        // elements it wrote (the strain comes out of the same plan at the
+        // same positions), so no barrier is needed.
+        constexpr bool PARK = xadj_park<PI, PF, U, R>();
+        cpx<R> a0[E], a1[E], a2[E], v[E];
+        cpx<R> ur[PARK ? 1 : 3][E];
+        cpx<R>* uv = twI + (SAME ? PI::tw_len : PI::tw_len + PF::tw_len) + u * 3 * N;
+        if constexpr (PARK) {
+#pragma unroll 1
+            for (int c = 0; c < 3; ++c) {
+                load_inv(5 + c, v);
+#pragma unroll
+                for (int i = 0; i < E; ++i) uv[c * N + PI::out_pos(t, i)] = v[i];
+            }
+        } else {
+            load_inv(5, ur[0]);
+            load_inv(6, ur[1]);
+            load_inv(7, ur[2]);
+        }
 #pragma unroll
         for (int i = 0; i < E; ++i) a0[i] = a1[i] = a2[i] = cpx<R>{0, 0};
-        auto fma2 = [&](cpx<R>(&acc)[E], const cpx<R>(&s)[E], const cpx<R>(&w)[E], R f) {
+        // acc += f S u_c
+        auto fma2 = [&](cpx<R>(&acc)[E], const cpx<R>(&s)[E], int c, R f) {
 #pragma unroll
             for (int i = 0; i < E; ++i) {
-                acc[i].x += f * s[i].x * w[i].x;
-                acc[i].y += f * s[i].y * w[i].y;
+                cpx<R> w;
+                if constexpr (PARK) w = uv[c * N + PI::out_pos(t, i)];
+                else w = c == 0 ? ur[0][i] : (c == 1 ? ur[1][i] : ur[2][i]);
+                acc[i].x += f * s[i].x * w.x;
+                acc[i].y += f * s[i].y * w.y;
             }
         };
 #pragma unroll 1
         for (int p = 0; p < 5; ++p) {
             load_inv(p, v);
             switch (p) {
-                case 0: fma2(a0, v, u0, 2); fma2(a2, v, u2, -2); break;
-                case 1: fma2(a0, v, u1, 2); fma2(a1, v, u0, 2); break;
-                case 2: fma2(a0, v, u2, 2); fma2(a2, v, u0, 2); break;
-                case 3: fma2(a1, v, u1, 2); fma2(a2, v, u2, -2); break;
-                default: fma2(a1, v, u2, 2); fma2(a2, v, u1, 2); break;
+                case 0: fma2(a0, v, 0, 2); fma2(a2, v, 2, -2); break;
+                case 1: fma2(a0, v, 1, 2); fma2(a1, v, 0, 2); break;
+                case 2: fma2(a0, v, 2, 2); fma2(a2, v, 0, 2); break;
+                case 3: fma2(a1, v, 1, 2); fma2(a2, v, 2, -2); break;
+                default: fma2(a1, v, 2, 2); fma2(a2, v, 1, 2); break;
             }
         }
         fwd_store(0, a0);
@@ -948,13 +977,14 @@ hipError_t launch_x(const XArgs& a, hipStream_t s)
     constexpr int XL = x_line_len<PI, PF, R>();
     static_assert(PI::G * U <= 1024, "at most 1024 threads per block");
     constexpr int TW = std::is_same<PI, PF>::value ? PI::tw_len : PI::tw_len + PF::tw_len;
-    static_assert(sizeof(cpx<R>) * (XL * U + TW) <= 163840, "LDS per block exceeds 160 KiB");
+    constexpr int PK = MODE == X_ADJ && xadj_park<PI, PF, U, R>() ? 3 * PI::N * U : 0;  // parked velocities
+    static_assert(sizeof(cpx<R>) * (XL * U + TW + PK) <= 163840, "LDS per block exceeds 160 KiB");
     static bool done = false;
     if (a.K != Cut<PI::N>::K) return hipErrorInvalidValue;
     long long grid = (a.nunits + U - 1) / U;
     if (BPC > 0 && grid > (long long)device_cus() * BPC) grid = (long long)device_cus() * BPC;
     return launch_k(k_xline<PI, PF, U, MODE, W, R, BPC, WS>, grid, PI::G * U,
-                    sizeof(cpx<R>) * (XL * U + TW), s, a, done);
+                    sizeof(cpx<R>) * (XL * U + TW + PK), s, a, done);
 }
 
 // x pass in the half-length form: a.nunits pairs of lines, i.e. 2 a.nunits lines
