@@ -96,6 +96,23 @@ struct F3Args {
     void* zinv;
 };
 
+// z-inverse pass of the adjoint's vector-Jacobian product: from the compact
+// adjoint state lam and velocity u (3 components each, column-blocked), the
+// five stored components of the trace-free strain of P lam and the three of
+// u, zero-padded to N rows and transformed along z, written as plain rows
+// [batch][8][N][MMx] (sample / component strides out_ss / out_cs).  Columns
+// are enumerated as batch * MMxp like the z pass.
+struct StrainZArgs {
+    const void* lam;
+    const void* u;
+    void* out;
+    const void* tw;
+    long long Q;               // batch * MMxp
+    int MMx, Mx, K, M;
+    long long st_ss, st_cs;    // compact sample stride (3 M MMxp) and component stride in a block (M CB)
+    long long out_ss, out_cs;  // 8 N MMx, N MMx
+};
+
 // Schedule variants of the tuned passes.
 constexpr int NS_MAXV = 12;
 struct ColVariant {
@@ -125,7 +142,8 @@ struct SizeKernels {
     hipError_t (*x_fwd3)(const XArgs&, hipStream_t);    // R2C of a real 3-component field
     hipError_t (*x_inv3)(const XArgs&, hipStream_t);    // C2R to a real 3-component field
     hipError_t (*f3_proj)(const F3Args&, hipStream_t);  // z forward of 3 comps + projection
-    hipError_t (*x_adj)(const XArgs&, hipStream_t);     // C2R of S (6) and u (3), a = 2 S u, R2C
+    hipError_t (*strain_z)(const StrainZArgs&, hipStream_t);  // strain of P lam (5) and u (3), inverse z
+    hipError_t (*x_adj)(const XArgs&, hipStream_t);     // C2R of S (5) and u (3), a = 2 S u, R2C
     hipError_t (*f3_adj)(const F3Args&, hipStream_t);   // z forward of 3 comps + adjoint epilogue
     const char* desc;
 };

@@ -160,48 +160,6 @@ __global__ void __launch_bounds__(SPEC_THREADS) k_spectrum(const cpx<R>* __restr
     if (threadIdx.x == 0 && kappa < kbins) E[kappa] = red[0];
 }
 
-// Symmetric strain of the projected adjoint (the transpose of the nonlinear
-// term): mu = P lam on each retained mode (compact layout, all samples), then
-// S_ij-hat = (i/2)(k_i mu_j + k_j mu_i) for (xx, xy, xz, yy, yz).  mu is
-// divergence-free, so the strain is trace-free and S_zz = -S_xx - S_yy is
-// not stored (the x pass forms it in physical space).
-template <typename R>
-__global__ void k_strain(const cpx<R>* __restrict__ lam, cpx<R>* __restrict__ S, int K, long long batch)
-{
-    constexpr int EB = sizeof(cpx<R>);
-    const int M = 2 * K + 1, Mx = K + 1;
-    const long long per = (long long)M * M * Mx, cols = compact_cols((long long)M * Mx, EB);
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= per * batch) return;
-    const long long b = idx / per, m = idx % per;
-    const long long sc = m % ((long long)M * Mx);
-    const int kxi = (int)(m % Mx), jy = (int)((m / Mx) % M), jz = (int)(m / ((long long)Mx * M));
-    const int kyi = jy <= K ? jy : jy - M, kzi = jz <= K ? jz : jz - M;
-    const R kv[3] = {(R)kxi, (R)kyi, (R)kzi};
-    // compact offsets: lam has 3 components per sample, S has 5
-    const cpx<R>* l = lam + b * 3 * M * cols + compact_off(EB, 3, M, 0, jz, sc);
-    const long long lcs = compact_off(EB, 3, M, 1, 0, 0);
-    cpx<R> mu[3] = {l[0], l[lcs], l[2 * lcs]};
-    const int k2 = kxi * kxi + kyi * kyi + kzi * kzi;
-    if (k2 > 0) {
-        const R inv = (R)1 / (R)k2;
-        const R bx = (kv[0] * mu[0].x + kv[1] * mu[1].x + kv[2] * mu[2].x) * inv;
-        const R by = (kv[0] * mu[0].y + kv[1] * mu[1].y + kv[2] * mu[2].y) * inv;
-        for (int c = 0; c < 3; ++c) {
-            mu[c].x -= kv[c] * bx;
-            mu[c].y -= kv[c] * by;
-        }
-    }
-    const int ti[5] = {0, 0, 0, 1, 1}, tj[5] = {0, 1, 2, 1, 2};
-    cpx<R>* o = S + b * 5 * M * cols + compact_off(EB, 5, M, 0, jz, sc);
-    const long long ocs = compact_off(EB, 5, M, 1, 0, 0);
-    for (int p = 0; p < 5; ++p) {
-        const int i = ti[p], j = tj[p];
-        const R wx = kv[i] * mu[j].x + kv[j] * mu[i].x, wy = kv[i] * mu[j].y + kv[j] * mu[i].y;
-        o[p * ocs] = {(R)-0.5 * wy, (R)0.5 * wx};  // (i/2) w
-    }
-}
-
 __global__ void k_fill(double* p, double v, long long n)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -478,14 +436,6 @@ hipError_t launch_fill_random(bool f64, void* p, long long nreal, unsigned long 
     if (nreal <= 0) return hipSuccess;
     if (f64) hipLaunchKernelGGL(k_fill_random<double>, dim3(nblocks(nreal, 256)), dim3(256), 0, s, (double*)p, nreal, seed);
     else hipLaunchKernelGGL(k_fill_random<float>, dim3(nblocks(nreal, 256)), dim3(256), 0, s, (float*)p, nreal, seed);
-    return hipGetLastError();
-}
-
-hipError_t launch_strain(bool f64, const void* lam, void* S, int K, long long batch, hipStream_t s)
-{
-    const long long total = batch * (2LL * K + 1) * (2LL * K + 1) * (K + 1);
-    if (f64) hipLaunchKernelGGL(k_strain<double>, dim3(nblocks(total, 256)), dim3(256), 0, s, (const cpx<double>*)lam, (cpx<double>*)S, K, batch);
-    else hipLaunchKernelGGL(k_strain<float>, dim3(nblocks(total, 256)), dim3(256), 0, s, (const cpx<float>*)lam, (cpx<float>*)S, K, batch);
     return hipGetLastError();
 }
 

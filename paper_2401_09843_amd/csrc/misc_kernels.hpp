@@ -24,7 +24,4 @@ hipError_t launch_w1(bool f64, const void* a, int na, const void* b, int nb, lon
                      double* mean, hipStream_t s);
 hipError_t launch_fill(double* p, double v, int n, hipStream_t s);
 hipError_t launch_fill_random(bool f64, void* p, long long nreal, unsigned long long seed, hipStream_t s);
-// the five stored components (xx, xy, xz, yy, yz) of the trace-free adjoint
-// strain of lam, both compact
-hipError_t launch_strain(bool f64, const void* lam, void* S, int K, long long batch, hipStream_t s);
 }  // namespace ns

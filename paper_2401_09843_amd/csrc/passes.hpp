@@ -910,6 +910,98 @@ __global__ void __launch_bounds__(P::G* T, W) k_f3(F3Args a)
     tile_body(col);
 }
 
+// ------------------------------------------------------------ adjoint z pass
+// The first pass of the adjoint's vector-Jacobian product: per tile of T
+// compact columns, lam and u are read once (three components each, the
+// retained rows), mu = P lam is formed in registers, and the five stored
+// components (xx, xy, xz, yy, yz) of the trace-free strain
+// S_ab = (i/2)(k_a mu_b + k_b mu_a) and the three of u are each transformed
+// back along z, zero-padded to N rows.  (The strain never goes to memory.)
+template <class P, int T, int SP, int W, typename R>
+__global__ void __launch_bounds__(P::G* T, W) k_strain_z(StrainZArgs a)
+{
+    constexpr int N = P::N, E = P::E;
+    constexpr int K = Cut<N>::K, M = Cut<N>::M, Mx = K + 1;
+    constexpr int CB = compact_cb(sizeof(cpx<R>));
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int TB = (int)tile_bytes<P, T, SP, R>();
+    cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
+    cpx<R>* twl = reinterpret_cast<cpx<R>*>(smem_raw + TB);
+    const int tid = threadIdx.x, c = tid % T, g = tid / T;
+    const long long cols = compact_cols(a.MMx, sizeof(cpx<R>));
+    const long long q = xcd_tile(gridDim.x) * T + c;
+    const bool valid = q < a.Q && q % cols < a.MMx;
+    const long long samp = valid ? q / cols : 0;
+    const int s = valid ? (int)(q % cols) : 0;
+    // compact offset of (component 0, row 0) of this column
+    const long long st0 = samp * a.st_ss + (long long)((unsigned)s / CB) * 3 * a.st_cs + (unsigned)s % CB;
+    auto load3 = [&](const void* src, cpx<R>(&v)[3][E]) {
+        const cpx<R>* __restrict__ p = static_cast<const cpx<R>*>(src) + st0;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int jz = compact_of(P::in_pos(g, i), N, K, M);
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                v[j][i] = (valid && jz >= 0) ? p[j * a.st_cs + (long long)jz * CB] : cpx<R>{0, 0};
+        }
+    };
+    cpx<R> mu[3][E];
+    load3(a.lam, mu);
+    P::template load_tw<R>(twl, static_cast<const cpx<R>*>(a.tw));
+    const int jy = s / Mx, kxi = s % Mx;
+    const R kx = (R)kxi, ky = (R)(jy <= K ? jy : jy - M);
+    // mu = P lam, mode by mode
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        const int n = P::in_pos(g, i);
+        const R kz = (R)(n < N / 2 ? n : n - N);
+        const R k2 = kx * kx + ky * ky + kz * kz;
+        if (k2 > 0) {
+            const R inv = (R)1 / k2;
+            const R dx = (kx * mu[0][i].x + ky * mu[1][i].x + kz * mu[2][i].x) * inv;
+            const R dy = (kx * mu[0][i].y + ky * mu[1][i].y + kz * mu[2][i].y) * inv;
+            mu[0][i] = {mu[0][i].x - kx * dx, mu[0][i].y - kx * dy};
+            mu[1][i] = {mu[1][i].x - ky * dx, mu[1][i].y - ky * dy};
+            mu[2][i] = {mu[2][i].x - kz * dx, mu[2][i].y - kz * dy};
+        }
+    }
+    auto transform_store = [&](int comp, cpx<R>(&v)[E]) {
+        int gg = g, cc = c;
+        asm volatile("" : "+v"(gg), "+v"(cc));
+        cpx<R>* base = SP ? reinterpret_cast<cpx<R>*>(reinterpret_cast<R*>(lds) + cc) : lds + cc;
+        P::template run<+1, T, SP>(v, gg, base, twl);
+        cpx<R>* o = static_cast<cpx<R>*>(a.out) + samp * a.out_ss + comp * a.out_cs + s;
+        if (valid) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) o[(long long)P::out_pos(gg, i) * a.MMx] = v[i];
+        }
+    };
+    // unrolled: a runtime component index would put mu in scratch memory
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+        // the pair (a, b) of strain component p: xx, xy, xz, yy, yz
+        const int ia = p < 3 ? 0 : 1, ib = p < 3 ? p : p - 2;
+        cpx<R> v[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int n = P::in_pos(g, i);
+            const R kz = (R)(n < N / 2 ? n : n - N);
+            const R ka = ia == 0 ? kx : ky;
+            const R kb = ib == 0 ? kx : (ib == 1 ? ky : kz);
+            const cpx<R> ma = ia == 0 ? mu[0][i] : mu[1][i];
+            const cpx<R> mb = ib == 0 ? mu[0][i] : (ib == 1 ? mu[1][i] : mu[2][i]);
+            const R wx = ka * mb.x + kb * ma.x, wy = ka * mb.y + kb * ma.y;
+            v[i] = {(R)-0.5 * wy, (R)0.5 * wx};  // (i/2) w
+        }
+        transform_store(p, v);
+    }
+    cpx<R> uv[3][E];
+    load3(a.u, uv);
+    transform_store(5, uv[0]);
+    transform_store(6, uv[1]);
+    transform_store(7, uv[2]);
+}
+
 // ------------------------------------------------------------------ launch
 template <typename Args>
 inline hipError_t launch_k(void (*k)(Args), long long blocks, int threads, size_t lds, hipStream_t s, const Args& a,
@@ -1012,6 +1104,17 @@ hipError_t launch_f3(const F3Args& a, hipStream_t s)
     return launch_k(k_f3<P, T, MODE, SP, W, R, PRE, ZI, DB>, (a.Q + T - 1) / T, P::G * T, lds, s, a, done);
 }
 
+template <class P, int T, int SP, int W, typename R>
+hipError_t launch_strain_z(const StrainZArgs& a, hipStream_t s)
+{
+    constexpr size_t lds = tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len;
+    static_assert(P::G * T <= 1024, "at most 1024 threads per block");
+    static_assert(lds <= 163840, "LDS per block exceeds 160 KiB");
+    static bool done = false;
+    if (!cut_ok<P::N>(a.K, a.M) || a.Mx != Cut<P::N>::K + 1) return hipErrorInvalidValue;
+    return launch_k(k_strain_z<P, T, SP, W, R>, (a.Q + T - 1) / T, P::G * T, lds, s, a, done);
+}
+
 template <class V, class F>
 inline void add_variant(V* list, int& n, F fn, const char* name)
 {
@@ -1053,6 +1156,7 @@ struct Launch {
         k.x_fwd3 = launch_x<PX, PXR, U, X_FWD3, 1, R>;
         k.x_inv3 = launch_x<PX, PXR, U, X_INV3, 1, R>;
         k.f3_proj = launch_f3<PF, TF, F3_PROJ, SPF, 1, R>;
+        k.strain_z = launch_strain_z<PF, TF, SPF, 1, R>;
         k.x_adj = launch_x<PX, PXR, U, X_ADJ, 1, R>;
         k.f3_adj = launch_f3<PF, TF, F3_ADJ, SPF, 1, R>;
         k.desc = C::desc;

@@ -75,8 +75,8 @@ struct Group {
     double *dt = nullptr, *ones = nullptr;
     std::vector<double> dt_host;  // values last uploaded to dt
     // adjoint buffers (allocated on first use): stage u2, adjoint stages,
-    // strain, and 9-component pass workspaces
-    void *U2 = nullptr, *L1 = nullptr, *L2 = nullptr, *L3 = nullptr, *Sb = nullptr, *A8 = nullptr, *B8 = nullptr;
+    // and 8-component pass workspaces
+    void *U2 = nullptr, *L1 = nullptr, *L2 = nullptr, *L3 = nullptr, *A8 = nullptr, *B8 = nullptr;
     int sel[NS_NPASS] = {0, 0, 0, 0, 0};  // chosen schedule variant per pass
     double tune_ms[NS_NPASS][NS_MAXV] = {};  // tuner timings (ms per launch), 0 = not timed
     // stage form: SSP-RK3 stages end in the fused F3 + inverse z pass (the
@@ -495,7 +495,6 @@ ns_status ensure_adjoint_buffers(ns_ctx* c, Group& g)
     if ((st = dalloc(c, &g.L1, cw * g.st * B))) return st;
     if ((st = dalloc(c, &g.L2, cw * g.st * B))) return st;
     if ((st = dalloc(c, &g.L3, cw * g.st * B))) return st;
-    if ((st = dalloc(c, &g.Sb, cw * 5ULL * g.M * g.MMxp * B))) return st;
     if ((st = dalloc(c, &g.A8, cw * 8ULL * N * g.MMx * B))) return st;
     if ((st = dalloc(c, &g.B8, cw * 8ULL * N * N * g.Mx * B))) return st;
     return NS_OK;
@@ -512,18 +511,13 @@ ns_status run_vjp(ns_ctx* c, Group& g, const void* u, const void* lam, void* out
     const SizeKernels* k = g.kern;
     const long long N = g.N, B = g.B, M = g.M, Mx = g.Mx, MMx = g.MMx;
     hipStream_t s = c->stream;
-    const size_t cw = cwb(c);
-    HIP_TRY(c, launch_strain(c->f64, lam, g.Sb, g.K, B, s));
-    // the column passes use the schedules chosen for the forward I1, I2, F2
-    const auto zinv = k->inv[g.sel[0]].fn, yinv = k->inv[g.sel[1]].fn, yfwd = k->fwd[g.sel[3]].fn;
-    // z: compact strain [B][5] and velocity [B][3] -> [B][8][N][MMx]
-    ColArgs s1{g.Sb, g.A8, g.tw, B * 5 * MMx, MMx, 5, 0, 0, N * MMx, 8 * N * MMx, g.K, g.M, 1.0};
-    compact_in(s1, g, 5);
-    HIP_TRY(c, zinv(s1, s));
-    ColArgs u1{u, (char*)g.A8 + cw * 5 * N * MMx, g.tw, B * 3 * MMx, MMx, 3, 0, 0, N * MMx, 8 * N * MMx, g.K, g.M,
-               1.0};
-    compact_in(u1, g, 3);
-    HIP_TRY(c, zinv(u1, s));
+    // the column passes use the schedules chosen for the forward I2, F2
+    const auto yinv = k->inv[g.sel[1]].fn, yfwd = k->fwd[g.sel[3]].fn;
+    // z: strain of P lam (5 components) and velocity (3), from compact lam
+    // and u, -> [B][8][N][MMx]
+    const StrainZArgs sz{lam, u, g.A8, g.tw, B * g.MMxp, (int)MMx, g.Mx, g.K, g.M, g.st, M * compact_cb(g.eb),
+                         8 * N * MMx, N * MMx};
+    HIP_TRY(c, k->strain_z(sz, s));
     // y: [B][8N][M][Mx] -> [B][8N][N][Mx]
     ColArgs y1{g.A8, g.B8, g.tw, B * 8 * N * Mx, Mx, 8 * N, M * Mx, 8 * N * M * Mx, N * Mx, 8 * N * N * Mx,
                g.K, g.M, 1.0};

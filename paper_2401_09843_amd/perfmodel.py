@@ -59,18 +59,19 @@ def step_bytes(n: int, real_bytes: int, fused: bool = False, steps_per_call: int
 def vjp_cw(n: int, stage: int) -> dict:
     """Complex words moved by one vector-Jacobian product of the right-hand
     side fused with adjoint RK3 stage `stage` (1: lambda_2, 2: lambda_1,
-    3: lambda_n), one sample: the strain of P lam (five stored components of
-    the trace-free strain), inverse z and y passes of those five and of the
-    three velocity components, the x pass forming 2 S u, forward y and z
-    passes of its three components, and the stage epilogue, which reads lam
-    and the earlier adjoint stages with nonzero coefficients (two arrays in
-    stages 1 and 2, three in stage 3) and writes one."""
+    3: lambda_n), one sample: a z pass that reads lam and u (three compact
+    components each), forms the five stored components of the trace-free
+    strain of P lam in registers and writes the inverse z transforms of
+    those five and of u, the inverse y pass of the eight, the x pass forming
+    2 S u, forward y and z passes of its three components, and the stage
+    epilogue, which reads lam and the earlier adjoint stages with nonzero
+    coefficients (two arrays in stages 1 and 2, three in stage 3) and
+    writes one."""
     K, M, Mx = dims(n)
     st = M * M * Mx
     reads = 3 if stage == 3 else 2
     return {
-        "strain": 3 * st + 5 * st,
-        "I1_inv_z": 8 * st + 8 * n * M * Mx,
+        "I1_inv_z": 6 * st + 8 * n * M * Mx,
         "I2_inv_y": 8 * n * M * Mx + 8 * n * n * Mx,
         "X_adj": 8 * n * n * Mx + 3 * n * n * Mx,
         "F2_fwd_y": 3 * n * n * Mx + 3 * n * M * Mx,

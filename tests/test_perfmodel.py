@@ -66,7 +66,7 @@ def test_fused_model():
 
 
 def test_adjoint_step_bytes_against_a_forward_step():
-    """An adjoint step (three VJPs from a tape) moves about 1.4 times the
+    """An adjoint step (three VJPs from a tape) moves about 1.3 times the
     bytes of a forward step: each VJP inverse-transforms eight fields (five
     strain components and three velocity components) where a right-hand
     side inverse-transforms three and forward-transforms six."""
@@ -74,8 +74,8 @@ def test_adjoint_step_bytes_against_a_forward_step():
 
     for n in (32, 128, 1024):
         r = perfmodel.adjoint_step_bytes(n, 8) / perfmodel.step_bytes(n, 8)
-        assert 1.3 < r < 1.45, (n, r)
+        assert 1.2 < r < 1.45, (n, r)
         K, M, Mx = perfmodel.dims(n)
         v = perfmodel.vjp_cw(n, 3)
-        assert v["strain"] == 8 * M * M * Mx
+        assert v["I1_inv_z"] == 6 * M * M * Mx + 8 * n * M * Mx  # lam and u in, eight fields out
         assert v["X_adj"] == 11 * n * n * Mx
