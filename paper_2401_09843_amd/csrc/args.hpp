@@ -114,7 +114,7 @@ struct StrainZArgs {
 };
 
 // Schedule variants of the tuned passes.
-constexpr int NS_MAXV = 12;
+constexpr int NS_MAXV = 16;
 struct ColVariant {
     hipError_t (*fn)(const ColArgs&, hipStream_t);
     const char* name;

@@ -470,6 +470,49 @@ struct Stages<N, G, DIR, PD, LS, SP, WS, DB, T, P, OFF, R, Rest...> {
                                                                                                       dbo, par);
         }
     }
+
+    // NV transforms of the same plan by the same thread, stage by stage:
+    // each twiddle factor is read from LDS once and applied to all NV
+    // (the exchanges still run one transform after the other through the
+    // one buffer)
+    template <int NV, typename L>
+    __device__ __forceinline__ static void run_n(cpx<T> (&v)[NV][E], int t, L* lds, const cpx<T>* __restrict__ tw,
+                                                 int dbo, int& par)
+    {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int b = t + q * G;
+            if constexpr (P > 1) {
+                const int k = b % P;
+#pragma unroll
+                for (int m = 1; m < R; ++m) {
+                    const cpx<T> w = tw[OFF + (m - 1) * P + k];
+#pragma unroll
+                    for (int j = 0; j < NV; ++j) v[j][q * R + m] = twiddle<DIR>(v[j][q * R + m], w);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NV; ++j) Dft<R, DIR, T>::run(&v[j][q * R]);
+        }
+        if constexpr (sizeof...(Rest) > 0) {
+            constexpr int R2 = Radices<Rest...>::first;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                if constexpr (lane_swap<R2>()) {
+                    swap_exchange(v[j], t);
+                } else if constexpr (SP == 0) {
+                    exchange<R2>(v[j], t, lds, [](cpx<T> a) { return a; }, [](cpx<T>& d, cpx<T> a) { d = a; }, dbo,
+                                 par);
+                } else {
+                    T* l = reinterpret_cast<T*>(lds);
+                    exchange<R2>(v[j], t, l, [](cpx<T> a) { return a.x; }, [](cpx<T>& d, T a) { d.x = a; }, dbo, par);
+                    exchange<R2>(v[j], t, l, [](cpx<T> a) { return a.y; }, [](cpx<T>& d, T a) { d.y = a; }, dbo, par);
+                }
+            }
+            Stages<N, G, DIR, PD, LS, SP, WS, DB, T, P * R, OFF + (P > 1 ? (R - 1) * P : 0), Rest...>::template run_n<NV>(
+                v, t, lds, tw, dbo, par);
+        }
+    }
 };
 
 // Per-stage twiddle tables in LDS: stage s with span P > 1 and radix R keeps
@@ -595,6 +638,16 @@ struct Plan<N_, G_, Radices<Rs...>> {
         static_assert(!WS || (G_ <= 64 && 64 % G_ == 0), "wavefront-synchronous exchanges need lines inside a wavefront");
         int par = 0;
         Stages<N_, G_, DIR, ST ? 0 : R0, LS, SP, WS, false, T, 1, 0, Rs...>::run(v, t, lds, tw, 0, par);
+    }
+    // the same for NV lines of one thread, transformed stage by stage with
+    // shared twiddle reads
+    template <int DIR, int LS, int SP = 0, bool ST = false, bool WS = false, int NV, typename T>
+    __device__ __forceinline__ static void run_n(cpx<T> (&v)[NV][E], int t, cpx<T>* lds, const cpx<T>* __restrict__ tw)
+    {
+        static_assert(!ST || (LS == 1 && SP == 0), "per-stage padding is laid out for one line at unit stride");
+        static_assert(!WS || (G_ <= 64 && 64 % G_ == 0), "wavefront-synchronous exchanges need lines inside a wavefront");
+        int par = 0;
+        Stages<N_, G_, DIR, ST ? 0 : R0, LS, SP, WS, false, T, 1, 0, Rs...>::template run_n<NV>(v, t, lds, tw, 0, par);
     }
     // the same with double-buffered exchanges (the second buffer dbo bytes
     // after the first; par selects the next buffer to write and is updated)

@@ -208,7 +208,11 @@ constexpr bool xadj_park()
 // that build the twiddle tables once and then walk the tiles of U units.
 // WS = true: the exchanges of a line synchronise its wavefront only (lines
 // of at most 64 threads lie inside one wavefront).
-template <class PI, class PF, int U, int MODE, int W, typename R, int BPC = 0, bool WS = false>
+// SHT (product pass) > 0: the three inverse transforms run stage by stage
+// together, so each twiddle factor is read from LDS once for all three; SHT
+// = 2 also groups the forward transforms of the products as xx | xy, xz |
+// yy, yz, zz (each group formed once the velocity it last needs is free).
+template <class PI, class PF, int U, int MODE, int W, typename R, int BPC = 0, bool WS = false, int SHT = 0>
 __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
 {
     constexpr int N = PI::N, G = PI::G, E = PI::E;
@@ -285,8 +289,9 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
     };
 
     // forward (R2C) of v = a + i b; store k_x <= K of both lines as product p
-    auto fwd_store = [&](int p, cpx<R>(&v)[E]) {
-        PF::template run<-1, 1, 0, true, WS>(v, t, my, twF);
+    // (v already transformed with SKIP)
+    auto fwd_store = [&](int p, cpx<R>(&v)[E], auto skip) {
+        if constexpr (!decltype(skip)::value) PF::template run<-1, 1, 0, true, WS>(v, t, my, twF);
 #pragma unroll
         for (int i = 0; i < E; ++i) my[PF::out_pos(t, i)] = v[i];
         lds_sync<WS>();
@@ -306,36 +311,64 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
 
     if constexpr (MODE == X_RHS) {
       auto body = [&] {
-        cpx<R> z0[E], z1[E], z2[E], v[E];
+        cpx<R> z[3][E], v[E];
         // all three loads in flight before the first transform
-        load_raw(0, z0);
-        load_raw(1, z1);
-        load_raw(2, z2);
+        load_raw(0, z[0]);
+        load_raw(1, z[1]);
+        load_raw(2, z[2]);
         if constexpr (STAGE) {
             PI::template put_tw<NT>(twI, ti);
             if constexpr (!SAME) PF::template put_tw<NT>(twF, tf);
             __syncthreads();
         }
-        PI::template run<+1, 1, 0, true, WS>(z0, t, my, twI);
-        PI::template run<+1, 1, 0, true, WS>(z1, t, my, twI);
-        PI::template run<+1, 1, 0, true, WS>(z2, t, my, twI);
+        if constexpr (SHT > 0) {
+            PI::template run_n<+1, 1, 0, true, WS>(z, t, my, twI);
+        } else {
+            PI::template run<+1, 1, 0, true, WS>(z[0], t, my, twI);
+            PI::template run<+1, 1, 0, true, WS>(z[1], t, my, twI);
+            PI::template run<+1, 1, 0, true, WS>(z[2], t, my, twI);
+        }
         // B_ij = u_i u_j, upper triangle (xx, xy, xz, yy, yz, zz); real parts
         // belong to line l1, imaginary parts to line l2
+        auto mul = [&](cpx<R>(&o)[E], const cpx<R>(&za)[E], const cpx<R>(&zb)[E]) {
 #pragma unroll
-        for (int p = 0; p < 6; ++p) {
-            auto mul = [&](const cpx<R>(&za)[E], const cpx<R>(&zb)[E]) {
-#pragma unroll
-                for (int i = 0; i < E; ++i) v[i] = {za[i].x * zb[i].x, za[i].y * zb[i].y};
-            };
-            switch (p) {
-                case 0: mul(z0, z0); break;
-                case 1: mul(z0, z1); break;
-                case 2: mul(z0, z2); break;
-                case 3: mul(z1, z1); break;
-                case 4: mul(z1, z2); break;
-                default: mul(z2, z2); break;
+            for (int i = 0; i < E; ++i) o[i] = {za[i].x * zb[i].x, za[i].y * zb[i].y};
+        };
+        if constexpr (SHT == 2) {
+            using T_ = std::true_type;
+            mul(v, z[0], z[0]);
+            fwd_store(0, v, std::false_type{});
+            {
+                cpx<R> w[2][E];
+                mul(w[0], z[0], z[1]);
+                mul(w[1], z[0], z[2]);
+                PF::template run_n<-1, 1, 0, true, WS>(w, t, my, twF);
+                fwd_store(1, w[0], T_{});
+                fwd_store(2, w[1], T_{});
             }
-            fwd_store(p, v);
+            {
+                cpx<R> w[3][E];
+                mul(w[0], z[1], z[1]);
+                mul(w[1], z[1], z[2]);
+                mul(w[2], z[2], z[2]);
+                PF::template run_n<-1, 1, 0, true, WS>(w, t, my, twF);
+                fwd_store(3, w[0], T_{});
+                fwd_store(4, w[1], T_{});
+                fwd_store(5, w[2], T_{});
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                switch (p) {
+                    case 0: mul(v, z[0], z[0]); break;
+                    case 1: mul(v, z[0], z[1]); break;
+                    case 2: mul(v, z[0], z[2]); break;
+                    case 3: mul(v, z[1], z[1]); break;
+                    case 4: mul(v, z[1], z[2]); break;
+                    default: mul(v, z[2], z[2]); break;
+                }
+                fwd_store(p, v, std::false_type{});
+            }
         }
       };
       if constexpr (BPC > 0) {
@@ -397,9 +430,9 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
                 default: fma2(a1, v, 2, 2); fma2(a2, v, 1, 2); break;
             }
         }
-        fwd_store(0, a0);
-        fwd_store(1, a1);
-        fwd_store(2, a2);
+        fwd_store(0, a0, std::false_type{});
+        fwd_store(1, a1, std::false_type{});
+        fwd_store(2, a2, std::false_type{});
     } else if constexpr (MODE == X_INV3) {
         cpx<R> v[E];
         for (int c = 0; c < 3; ++c) {
@@ -423,7 +456,7 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
                 const int x = PF::in_pos(t, i);
                 v[i] = valid ? cpx<R>{p1[x], p1[N + x]} : cpx<R>{0, 0};
             }
-            fwd_store(c, v);
+            fwd_store(c, v, std::false_type{});
         }
     }
 }
@@ -441,7 +474,8 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
 // which are the even-sample and odd-sample transforms recombined.  A lane
 // holds the same positions k = t + G i at the input and the output of the
 // plan, so one register set of W^k serves both.
-template <class PH, int U, int W, typename R>
+// SHT as for k_xline (2: inverse and forward transforms grouped).
+template <class PH, int U, int W, typename R, int SHT = 0>
 __global__ void __launch_bounds__(PH::G* U, W) k_xhalf(XArgs a)
 {
     constexpr int H = PH::N, N = 2 * H, G = PH::G, E = PH::E;
@@ -490,8 +524,8 @@ __global__ void __launch_bounds__(PH::G* U, W) k_xhalf(XArgs a)
         }
     };
     // forward transform of the packed product v, then Y_k, k <= K, of product p
-    auto fwd_store = [&](int p, cpx<R>(&v)[E]) {
-        PH::template run<-1, 1, 0, true, true>(v, t, my, twl);
+    auto fwd_store = [&](int p, cpx<R>(&v)[E], auto skip) {
+        if constexpr (!decltype(skip)::value) PH::template run<-1, 1, 0, true, true>(v, t, my, twl);
 #pragma unroll
         for (int i = 0; i < E; ++i) my[PH::out_pos(t, i)] = v[i];
         lds_sync<true>();
@@ -511,30 +545,58 @@ __global__ void __launch_bounds__(PH::G* U, W) k_xhalf(XArgs a)
     };
     static_assert(K < E * G, "the lane's W^k set covers the stored modes");
 
-    cpx<R> z0[E], z1[E], z2[E], v[E];
-    load_z(0, z0);
-    load_z(1, z1);
-    load_z(2, z2);
-    PH::template run<+1, 1, 0, true, true>(z0, t, my, twl);
-    PH::template run<+1, 1, 0, true, true>(z1, t, my, twl);
-    PH::template run<+1, 1, 0, true, true>(z2, t, my, twl);
+    cpx<R> z[3][E], v[E];
+    load_z(0, z[0]);
+    load_z(1, z[1]);
+    load_z(2, z[2]);
+    if constexpr (SHT > 0) {
+        PH::template run_n<+1, 1, 0, true, true>(z, t, my, twl);
+    } else {
+        PH::template run<+1, 1, 0, true, true>(z[0], t, my, twl);
+        PH::template run<+1, 1, 0, true, true>(z[1], t, my, twl);
+        PH::template run<+1, 1, 0, true, true>(z[2], t, my, twl);
+    }
     // B_ij = u_i u_j (xx, xy, xz, yy, yz, zz): real parts are the even
     // samples, imaginary parts the odd ones
+    auto mul = [&](cpx<R>(&o)[E], const cpx<R>(&za)[E], const cpx<R>(&zb)[E]) {
 #pragma unroll
-    for (int p = 0; p < 6; ++p) {
-        auto mul = [&](const cpx<R>(&za)[E], const cpx<R>(&zb)[E]) {
-#pragma unroll
-            for (int i = 0; i < E; ++i) v[i] = {za[i].x * zb[i].x, za[i].y * zb[i].y};
-        };
-        switch (p) {
-            case 0: mul(z0, z0); break;
-            case 1: mul(z0, z1); break;
-            case 2: mul(z0, z2); break;
-            case 3: mul(z1, z1); break;
-            case 4: mul(z1, z2); break;
-            default: mul(z2, z2); break;
+        for (int i = 0; i < E; ++i) o[i] = {za[i].x * zb[i].x, za[i].y * zb[i].y};
+    };
+    if constexpr (SHT == 2) {
+        using T_ = std::true_type;
+        mul(v, z[0], z[0]);
+        fwd_store(0, v, std::false_type{});
+        {
+            cpx<R> w[2][E];
+            mul(w[0], z[0], z[1]);
+            mul(w[1], z[0], z[2]);
+            PH::template run_n<-1, 1, 0, true, true>(w, t, my, twl);
+            fwd_store(1, w[0], T_{});
+            fwd_store(2, w[1], T_{});
         }
-        fwd_store(p, v);
+        {
+            cpx<R> w[3][E];
+            mul(w[0], z[1], z[1]);
+            mul(w[1], z[1], z[2]);
+            mul(w[2], z[2], z[2]);
+            PH::template run_n<-1, 1, 0, true, true>(w, t, my, twl);
+            fwd_store(3, w[0], T_{});
+            fwd_store(4, w[1], T_{});
+            fwd_store(5, w[2], T_{});
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            switch (p) {
+                case 0: mul(v, z[0], z[0]); break;
+                case 1: mul(v, z[0], z[1]); break;
+                case 2: mul(v, z[0], z[2]); break;
+                case 3: mul(v, z[1], z[1]); break;
+                case 4: mul(v, z[1], z[2]); break;
+                default: mul(v, z[2], z[2]); break;
+            }
+            fwd_store(p, v, std::false_type{});
+        }
     }
 }
 
@@ -1063,7 +1125,7 @@ hipError_t launch_col_p(const ColArgs& a, hipStream_t s)
                     tile_bytes<P, T, SP, R>() + sizeof(cpx<R>) * P::tw_len, s, a, done);
 }
 
-template <class PI, class PF, int U, int MODE, int W, typename R, int BPC = 0, bool WS = false>
+template <class PI, class PF, int U, int MODE, int W, typename R, int BPC = 0, bool WS = false, int SHT = 0>
 hipError_t launch_x(const XArgs& a, hipStream_t s)
 {
     constexpr int XL = x_line_len<PI, PF, R>();
@@ -1075,12 +1137,12 @@ hipError_t launch_x(const XArgs& a, hipStream_t s)
     if (a.K != Cut<PI::N>::K) return hipErrorInvalidValue;
     long long grid = (a.nunits + U - 1) / U;
     if (BPC > 0 && grid > (long long)device_cus() * BPC) grid = (long long)device_cus() * BPC;
-    return launch_k(k_xline<PI, PF, U, MODE, W, R, BPC, WS>, grid, PI::G * U,
+    return launch_k(k_xline<PI, PF, U, MODE, W, R, BPC, WS, SHT>, grid, PI::G * U,
                     sizeof(cpx<R>) * (XL * U + TW + PK), s, a, done);
 }
 
 // x pass in the half-length form: a.nunits pairs of lines, i.e. 2 a.nunits lines
-template <class PH, int U, int W, typename R>
+template <class PH, int U, int W, typename R, int SHT = 0>
 hipError_t launch_xh(const XArgs& a, hipStream_t s)
 {
     constexpr int LL = PH::template lds_len_st<sizeof(cpx<R>)>();
@@ -1089,7 +1151,7 @@ hipError_t launch_xh(const XArgs& a, hipStream_t s)
     static_assert(lds <= 163840, "LDS per block exceeds 160 KiB");
     static bool done = false;
     if (a.K != (2 * PH::N - 1) / 3) return hipErrorInvalidValue;
-    return launch_k(k_xhalf<PH, U, W, R>, (2 * a.nunits + U - 1) / U, PH::G * U, lds, s, a, done);
+    return launch_k(k_xhalf<PH, U, W, R, SHT>, (2 * a.nunits + U - 1) / U, PH::G * U, lds, s, a, done);
 }
 
 template <class P, int T, int MODE, int SP, int W, typename R, int PRE = 0, int ZI = 0, int DB = 0>

@@ -28,13 +28,17 @@ SizeKernels make32()
     add_x<PB, PBR, 2, 3, R>(k, "G128 r8.8.4.4 U2 w3");
     add_x<PB, PBR, 2, 4, R>(k, "G128 r8.8.4.4 U2 w4");
     add_x<PE, PE, 2, 4, R>(k, "G128 r4.8.8.4 U2 w4");
-    add_x<PB, PBR, 1, 1, R>(k, "G128 r8.8.4.4 U1");
+    add_x_sht<PB, PBR, 2, 4, R>(k, "G128 r8.8.4.4 U2 w4 sht");
+    add_x_sht<PB, PBR, 2, 4, R, false, 2>(k, "G128 r8.8.4.4 U2 w4 sht2");
+    add_x_sht<PE, PE, 2, 5, R, false, 2>(k, "G128 r4.8.8.4 U2 w5 sht2");
+    add_x_sht<PE, PE, 2, 4, R, false, 2>(k, "G128 r4.8.8.4 U2 w4 sht2");
+    add_x_sht<PE, PE, 2, 4, R>(k, "G128 r4.8.8.4 U2 w4 sht");
     add_x<PB, PBR, 2, 4, R, 4>(k, "persistent G128 r8.8.4.4 U2 w4 x4");
     add_x<PD, PD, 2, 1, R>(k, "G256 r4.4.4.4.4 U2");
-    add_x<PD, PD, 1, 1, R>(k, "G256 r4.4.4.4.4 U1");
     add_x<PE, PE, 2, 1, R>(k, "G128 r4.8.8.4 U2");
     add_xh<PH, 4, 1, R>(k, "half G64 r8.8.8 U4");
     add_xh<PH, 4, 4, R>(k, "half G64 r8.8.8 U4 w4");
+    add_xh<PH, 4, 4, R, 2>(k, "half G64 r8.8.8 U4 w4 sht2");
     add_f3<PB, 4, 1, 1, R, 1>(k, "G128 r8.8.4.4 T4 split prefetch");
     add_f3<PB, 8, 0, 1, R, 1>(k, "G128 r8.8.4.4 T8 prefetch");
     add_f3<PE, 8, 0, 1, R, 1>(k, "G128 r4.8.8.4 T8 prefetch");

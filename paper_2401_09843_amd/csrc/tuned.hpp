@@ -18,17 +18,25 @@ void add_col_p(SizeKernels& k, const char* name)
     add_variant(k.fwd, k.n_fwd, launch_col_p<P, T, -1, COL_FWD_TRUNC, SP, W, BPC, R>, name);
 }
 
-template <class PI, class PF, int U, int W, typename R, int BPC = 0, bool WS = false>
+template <class PI, class PF, int U, int W, typename R, int BPC = 0, bool WS = false, int SHT = 0>
 void add_x(SizeKernels& k, const char* name)
 {
-    add_variant(k.x, k.n_x, launch_x<PI, PF, U, X_RHS, W, R, BPC, WS>, name);
+    add_variant(k.x, k.n_x, launch_x<PI, PF, U, X_RHS, W, R, BPC, WS, SHT>, name);
+}
+
+// the product x pass with transforms grouped to share twiddle reads: the
+// three inverse ones (SHT = 1), and the forward ones too (SHT = 2)
+template <class PI, class PF, int U, int W, typename R, bool WS = false, int SHT = 1>
+void add_x_sht(SizeKernels& k, const char* name)
+{
+    add_variant(k.x, k.n_x, launch_x<PI, PF, U, X_RHS, W, R, 0, WS, SHT>, name);
 }
 
 // the x pass in the half-length form (one wavefront per line)
-template <class PH, int U, int W, typename R>
+template <class PH, int U, int W, typename R, int SHT = 0>
 void add_xh(SizeKernels& k, const char* name)
 {
-    add_variant(k.x, k.n_x, launch_xh<PH, U, W, R>, name);
+    add_variant(k.x, k.n_x, launch_xh<PH, U, W, R, SHT>, name);
 }
 
 // the x pass with wavefront-synchronous exchanges (lines of at most 64 threads)
