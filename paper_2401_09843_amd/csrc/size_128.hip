@@ -10,6 +10,7 @@ using PBR = Plan<128, 16, Radices<2, 8, 8>>;
 using PC = Plan<128, 32, Radices<4, 4, 4, 2>>;
 using PCR = Plan<128, 32, Radices<2, 4, 4, 4>>;
 using PH = Plan<64, 8, Radices<8, 8>>;  // half-length x lines
+using PS = Plan<128, 16, Radices<8, 2, 8>>;  // one plan for both x-pass halves
 
 SizeKernels make32()
 {
@@ -21,6 +22,8 @@ SizeKernels make32()
     add_x<PB, PBR, 8, 1, R>(k, "G16 r8.8.2 U8");
     add_x_sht<PB, PBR, 8, 1, R>(k, "G16 r8.8.2 U8 sht");
     add_x_sht<PB, PBR, 8, 1, R, false, 2>(k, "G16 r8.8.2 U8 sht2");
+    add_x_sht<PS, PS, 8, 1, R>(k, "G16 r8.2.8 U8 sht");
+    add_x_sht<PS, PS, 8, 1, R, false, 2>(k, "G16 r8.2.8 U8 sht2");
     add_x<PC, PCR, 4, 1, R>(k, "G32 r4.4.4.2 U4");
     add_x<PA, Plan<128, 8, Radices<8, 16>>, 16, 1, R>(k, "G8 r16.8 U16");
     add_x_ws<PB, PBR, 8, 1, R>(k, "G16 r8.8.2 U8 wave");
