@@ -322,6 +322,24 @@ __device__ __forceinline__ void lds_sync()
 // to write next.  Every thread then finishes reading an exchange's buffer
 // before it can pass the barrier of the following exchange, which writes
 // the other buffer, so the barrier after the reads is not needed.
+// A butterfly order for lines of 128 threads (two wavefronts) in which
+// butterflies b and (128 - b) mod 128 always lie in the same wavefront:
+// wavefront 0 takes 0..31, 97..127 and 64, wavefront 1 takes 32..63 and
+// 65..96.  mirror_lane(b) is the lane (within its wavefront) of butterfly b.
+__device__ __forceinline__ int mirror_order(int t)
+{
+    const int l = t & 63;
+    if (t < 64) return l < 32 ? l : (l < 63 ? l + 65 : 64);
+    return l < 32 ? l + 32 : l + 33;
+}
+__device__ __forceinline__ int mirror_lane(int b)
+{
+    if (b < 32) return b;
+    if (b < 64) return b - 32;
+    if (b == 64) return 63;
+    return b < 97 ? b - 33 : b - 65;
+}
+
 template <int N, int G, int DIR, int PD, int LS, int SP, bool WS, bool DB, typename T, int P, int OFF, int... Rs>
 struct Stages;
 
@@ -352,9 +370,11 @@ struct Stages<N, G, DIR, PD, LS, SP, WS, DB, T, P, OFF, R, Rest...> {
         return G % PER == 0 && (N / R2) % PER == 0;
     }
 
+    // (tr: the thread index that reads, i.e. the butterfly index this thread
+    // takes in the next stage; t otherwise)
     template <int R2, typename L, typename Get, typename Put>
     __device__ __forceinline__ static void exchange(cpx<T> (&v)[E], int t, L* lds0, Get get, Put put, int dbo,
-                                                    int& par)
+                                                    int& par, int tr)
     {
         constexpr int ES = sizeof(L);
         L* lds = lds0;
@@ -378,7 +398,7 @@ struct Stages<N, G, DIR, PD, LS, SP, WS, DB, T, P, OFF, R, Rest...> {
         }
         lds_sync<WS>();
         if constexpr (fast_read<R2, ES>()) {
-            const L* base = lds + lds_slot<PD, P, R, ES>(t) * LS;
+            const L* base = lds + lds_slot<PD, P, R, ES>(tr) * LS;
 #pragma unroll
             for (int q = 0; q < N / (R2 * G); ++q)
 #pragma unroll
@@ -389,7 +409,7 @@ struct Stages<N, G, DIR, PD, LS, SP, WS, DB, T, P, OFF, R, Rest...> {
             for (int q = 0; q < N / (R2 * G); ++q)
 #pragma unroll
                 for (int m = 0; m < R2; ++m)
-                    put(v[q * R2 + m], lds[lds_slot<PD, P, R, ES>(t + q * G + m * (N / R2)) * LS]);
+                    put(v[q * R2 + m], lds[lds_slot<PD, P, R, ES>(tr + q * G + m * (N / R2)) * LS]);
         }
         if constexpr (DB) par ^= 1;
         else lds_sync<WS>();
@@ -460,11 +480,11 @@ struct Stages<N, G, DIR, PD, LS, SP, WS, DB, T, P, OFF, R, Rest...> {
             if constexpr (lane_swap<R2>()) {
                 swap_exchange(v, t);
             } else if constexpr (SP == 0) {
-                exchange<R2>(v, t, lds, [](cpx<T> a) { return a; }, [](cpx<T>& d, cpx<T> a) { d = a; }, dbo, par);
+                exchange<R2>(v, t, lds, [](cpx<T> a) { return a; }, [](cpx<T>& d, cpx<T> a) { d = a; }, dbo, par, t);
             } else {
                 T* l = reinterpret_cast<T*>(lds);
-                exchange<R2>(v, t, l, [](cpx<T> a) { return a.x; }, [](cpx<T>& d, T a) { d.x = a; }, dbo, par);
-                exchange<R2>(v, t, l, [](cpx<T> a) { return a.y; }, [](cpx<T>& d, T a) { d.y = a; }, dbo, par);
+                exchange<R2>(v, t, l, [](cpx<T> a) { return a.x; }, [](cpx<T>& d, T a) { d.x = a; }, dbo, par, t);
+                exchange<R2>(v, t, l, [](cpx<T> a) { return a.y; }, [](cpx<T>& d, T a) { d.y = a; }, dbo, par, t);
             }
             Stages<N, G, DIR, PD, LS, SP, WS, DB, T, P * R, OFF + (P > 1 ? (R - 1) * P : 0), Rest...>::run(v, t, lds, tw,
                                                                                                       dbo, par);
@@ -475,10 +495,14 @@ struct Stages<N, G, DIR, PD, LS, SP, WS, DB, T, P, OFF, R, Rest...> {
     // each twiddle factor is read from LDS once and applied to all NV
     // (the exchanges still run one transform after the other through the
     // one buffer)
-    template <int NV, typename L>
+    // MIR = true: the last stage takes butterfly mirror_order(t) instead of
+    // t (lines of 128 threads), so that butterflies b and G - b, whose
+    // outputs hold the bins k and N - k, lie in the same wavefront.
+    template <int NV, bool MIR = false, typename L>
     __device__ __forceinline__ static void run_n(cpx<T> (&v)[NV][E], int t, L* lds, const cpx<T>* __restrict__ tw,
                                                  int dbo, int& par)
     {
+        static_assert(!MIR || (G == 128 && SP == 0), "mirrored last stage for lines of 128 threads");
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             const int b = t + q * G;
@@ -496,21 +520,25 @@ struct Stages<N, G, DIR, PD, LS, SP, WS, DB, T, P, OFF, R, Rest...> {
         }
         if constexpr (sizeof...(Rest) > 0) {
             constexpr int R2 = Radices<Rest...>::first;
+            const int tn = MIR && sizeof...(Rest) == 1 ? mirror_order(t) : t;
 #pragma unroll
             for (int j = 0; j < NV; ++j) {
-                if constexpr (lane_swap<R2>()) {
+                if constexpr (lane_swap<R2>() && !MIR) {
                     swap_exchange(v[j], t);
                 } else if constexpr (SP == 0) {
                     exchange<R2>(v[j], t, lds, [](cpx<T> a) { return a; }, [](cpx<T>& d, cpx<T> a) { d = a; }, dbo,
-                                 par);
+                                 par, tn);
                 } else {
                     T* l = reinterpret_cast<T*>(lds);
-                    exchange<R2>(v[j], t, l, [](cpx<T> a) { return a.x; }, [](cpx<T>& d, T a) { d.x = a; }, dbo, par);
-                    exchange<R2>(v[j], t, l, [](cpx<T> a) { return a.y; }, [](cpx<T>& d, T a) { d.y = a; }, dbo, par);
+                    exchange<R2>(v[j], t, l, [](cpx<T> a) { return a.x; }, [](cpx<T>& d, T a) { d.x = a; }, dbo, par,
+                                 tn);
+                    exchange<R2>(v[j], t, l, [](cpx<T> a) { return a.y; }, [](cpx<T>& d, T a) { d.y = a; }, dbo, par,
+                                 tn);
                 }
             }
-            Stages<N, G, DIR, PD, LS, SP, WS, DB, T, P * R, OFF + (P > 1 ? (R - 1) * P : 0), Rest...>::template run_n<NV>(
-                v, t, lds, tw, dbo, par);
+            Stages<N, G, DIR, PD, LS, SP, WS, DB, T, P * R, OFF + (P > 1 ? (R - 1) * P : 0), Rest...>::template run_n<NV,
+                                                                                                              MIR>(
+                v, tn, lds, tw, dbo, par);
         }
     }
 };
@@ -641,13 +669,16 @@ struct Plan<N_, G_, Radices<Rs...>> {
     }
     // the same for NV lines of one thread, transformed stage by stage with
     // shared twiddle reads
-    template <int DIR, int LS, int SP = 0, bool ST = false, bool WS = false, int NV, typename T>
+    // MIR = true: the last stage runs in mirror_order (its outputs for
+    // thread t are X[mirror_order(t) + m N / RL])
+    template <int DIR, int LS, int SP = 0, bool ST = false, bool WS = false, bool MIR = false, int NV, typename T>
     __device__ __forceinline__ static void run_n(cpx<T> (&v)[NV][E], int t, cpx<T>* lds, const cpx<T>* __restrict__ tw)
     {
         static_assert(!ST || (LS == 1 && SP == 0), "per-stage padding is laid out for one line at unit stride");
         static_assert(!WS || (G_ <= 64 && 64 % G_ == 0), "wavefront-synchronous exchanges need lines inside a wavefront");
         int par = 0;
-        Stages<N_, G_, DIR, ST ? 0 : R0, LS, SP, WS, false, T, 1, 0, Rs...>::template run_n<NV>(v, t, lds, tw, 0, par);
+        Stages<N_, G_, DIR, ST ? 0 : R0, LS, SP, WS, false, T, 1, 0, Rs...>::template run_n<NV, MIR>(v, t, lds, tw, 0,
+                                                                                                 par);
     }
     // the same with double-buffered exchanges (the second buffer dbo bytes
     // after the first; par selects the next buffer to write and is updated)

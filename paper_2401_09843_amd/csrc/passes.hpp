@@ -212,6 +212,10 @@ constexpr bool xadj_park()
 // together, so each twiddle factor is read from LDS once for all three; SHT
 // = 2 also groups the forward transforms of the products as xx | xy, xz |
 // yy, yz, zz (each group formed once the velocity it last needs is free).
+// SHT = 3 (lines of 128 threads, last forward radix E): as 2, with the
+// forward transforms' last stage in mirror_order, so that each thread gets
+// Z_{N-k} for its bins k from a lane of its own wavefront (ds_bpermute)
+// and the R2C unpack needs no LDS buffer and no barrier.
 template <class PI, class PF, int U, int MODE, int W, typename R, int BPC = 0, bool WS = false, int SHT = 0>
 __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
 {
@@ -309,6 +313,40 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
         lds_sync<WS>();
     };
 
+    // SHT = 3: v holds Z[b + m G], b = mirror_order(t), m < E; the partner
+    // lane (bins G - b) holds Z[N - b - m G] in slot E - 1 - m
+    auto fwd_store_mir = [&](int p, const cpx<R>(&v)[E]) {
+        static_assert(SHT != 3 || (G == 128 && PF::RL == E && N == E * G && K < 3 * G), "mirrored unpack: 128-thread lines, last radix E");
+        const int b = mirror_order(t);
+        const int pl = 4 * mirror_lane((G - b) & (G - 1));
+        auto bp = [&](R x) {
+            if constexpr (sizeof(R) == 4) {
+                return __builtin_bit_cast(R, __builtin_amdgcn_ds_bpermute(pl, __builtin_bit_cast(int, x)));
+            } else {
+                const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+                const unsigned lo = (unsigned)__builtin_amdgcn_ds_bpermute(pl, (int)(unsigned)u);
+                const unsigned hi = (unsigned)__builtin_amdgcn_ds_bpermute(pl, (int)(unsigned)(u >> 32));
+                return __builtin_bit_cast(R, ((unsigned long long)hi << 32) | lo);
+            }
+        };
+        cpx<R> pm[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) pm[m] = {bp(v[E - 1 - m].x), bp(v[E - 1 - m].y)};
+        const R h = (R)(0.5 * a.scale);
+        cpx<R>* o1 = static_cast<cpx<R>*>(a.out) + samp * a.out_ss + p * a.out_cs + l1 * Mx;
+        cpx<R>* o2 = o1 + Mx;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const int kx = b + m * G;
+            const cpx<R> zk = v[m];
+            const cpx<R> zm = b == 0 ? v[(E - m) % E] : pm[m];  // bin 0 mirrors onto its own thread
+            if (valid && kx <= K) {
+                o1[kx] = {(zk.x + zm.x) * h, (zk.y - zm.y) * h};
+                o2[kx] = {(zk.y + zm.y) * h, (zm.x - zk.x) * h};
+            }
+        }
+    };
+
     if constexpr (MODE == X_RHS) {
       auto body = [&] {
         cpx<R> z[3][E], v[E];
@@ -334,7 +372,33 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
 #pragma unroll
             for (int i = 0; i < E; ++i) o[i] = {za[i].x * zb[i].x, za[i].y * zb[i].y};
         };
-        if constexpr (SHT == 2) {
+        if constexpr (SHT == 3) {
+            auto fwd = [&](auto& w) { PF::template run_n<-1, 1, 0, true, WS, true>(w, t, my, twF); };
+            {
+                cpx<R> w[1][E];
+                mul(w[0], z[0], z[0]);
+                fwd(w);
+                fwd_store_mir(0, w[0]);
+            }
+            {
+                cpx<R> w[2][E];
+                mul(w[0], z[0], z[1]);
+                mul(w[1], z[0], z[2]);
+                fwd(w);
+                fwd_store_mir(1, w[0]);
+                fwd_store_mir(2, w[1]);
+            }
+            {
+                cpx<R> w[3][E];
+                mul(w[0], z[1], z[1]);
+                mul(w[1], z[1], z[2]);
+                mul(w[2], z[2], z[2]);
+                fwd(w);
+                fwd_store_mir(3, w[0]);
+                fwd_store_mir(4, w[1]);
+                fwd_store_mir(5, w[2]);
+            }
+        } else if constexpr (SHT == 2) {
             using T_ = std::true_type;
             mul(v, z[0], z[0]);
             fwd_store(0, v, std::false_type{});

@@ -37,8 +37,9 @@ SizeKernels make32()
     add_x_sht<PE, PE, 2, 4, R>(k, "G128 r4.8.8.4 U2 w4 sht");
     add_x_sht<PS, PS, 1, 4, R, false, 2>(k, "G128 r8.4.4.8 U1 w4 sht2");
     add_x_sht<PS, PS, 2, 4, R, false, 2>(k, "G128 r8.4.4.8 U2 w4 sht2");
+    add_x_sht<PS, PS, 1, 4, R, false, 3>(k, "G128 r8.4.4.8 U1 w4 sht2 mirror");
+    add_x_sht<PS, PS, 2, 4, R, false, 3>(k, "G128 r8.4.4.8 U2 w4 sht2 mirror");
     add_x<PB, PBR, 2, 4, R, 4>(k, "persistent G128 r8.8.4.4 U2 w4 x4");
-    add_x<PD, PD, 2, 1, R>(k, "G256 r4.4.4.4.4 U2");
     add_xh<PH, 4, 1, R>(k, "half G64 r8.8.8 U4");
     add_xh<PH, 4, 4, R>(k, "half G64 r8.8.8 U4 w4");
     add_xh<PH, 4, 4, R, 2>(k, "half G64 r8.8.8 U4 w4 sht2");
