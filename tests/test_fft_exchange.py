@@ -60,3 +60,73 @@ def test_wider_spans_keep_the_values_in_their_lane(N, radices):
         b = t + q * G
         for p in (b, b + N // 2):
             assert pos[p][0] == t
+
+
+# ------------------------------------------------------------ mirrored order
+# The x pass's grouped forward transforms can run their last stage with
+# butterfly mirror_order(t) on thread t (lines of 128 threads, last radix
+# E = 8), so that a thread's bins k = b + 128 m and the bins N - k it needs
+# for the real-to-complex unpack lie in one wavefront.  These restate the
+# engine's two index functions and check the properties the unpack relies on.
+def mirror_order(t):
+    l = t & 63
+    if t < 64:
+        return l if l < 32 else (l + 65 if l < 63 else 64)
+    return l + 32 if l < 32 else l + 33
+
+
+def mirror_lane(b):
+    if b < 32:
+        return b
+    if b < 64:
+        return b - 32
+    if b == 64:
+        return 63
+    return b - 33 if b < 97 else b - 65
+
+
+def test_mirror_order_is_a_permutation_with_mirror_pairs_in_one_wavefront():
+    G = 128
+    order = [mirror_order(t) for t in range(G)]
+    assert sorted(order) == list(range(G))
+    for t in range(G):
+        b = order[t]
+        assert mirror_lane(b) == t % 64
+        partner = (G - b) % G
+        tp = order.index(partner)
+        assert tp // 64 == t // 64, (t, b, partner)  # same wavefront
+        assert mirror_lane(partner) == tp % 64
+
+
+@pytest.mark.parametrize("N, radices", [(1024, (8, 4, 4, 8))])
+def test_mirrored_last_stage_gives_each_bin_its_mirror_in_a_partner_slot(N, radices):
+    """Run the Stockham index maps with the last stage on butterfly
+    mirror_order(t): thread t then holds X[b + 128 m] in slot m, and bin
+    N - (b + 128 m) sits in slot E - 1 - m of the partner lane (b != 0) or in
+    slot (E - m) mod E of the thread itself (b = 0)."""
+    G = 128
+    E = N // G
+    R = radices[-1]
+    assert R == E
+    held = {}
+    for t in range(G):
+        b = mirror_order(t)
+        for m in range(R):
+            held[b + m * (N // R)] = (t, m)
+    assert sorted(held) == list(range(N))
+    K = (N - 1) // 3
+    for t in range(G):
+        b = mirror_order(t)
+        lane = t % 64
+        for m in range(3):
+            k = b + m * G
+            if k > K:
+                continue
+            src_t, src_slot = held[(N - k) % N]
+            if b == 0:
+                assert (src_t, src_slot) == (t, (E - m) % E)
+            else:
+                assert src_t // 64 == t // 64
+                assert src_t % 64 == mirror_lane((G - b) % G)
+                assert src_slot == E - 1 - m
+        assert lane == mirror_lane(b)
