@@ -212,10 +212,11 @@ constexpr bool xadj_park()
 // together, so each twiddle factor is read from LDS once for all three; SHT
 // = 2 also groups the forward transforms of the products as xx | xy, xz |
 // yy, yz, zz (each group formed once the velocity it last needs is free).
-// SHT = 3 (lines of 128 threads, last forward radix E): as 2, with the
-// forward transforms' last stage in mirror_order, so that each thread gets
-// Z_{N-k} for its bins k from a lane of its own wavefront (ds_bpermute)
-// and the R2C unpack needs no LDS buffer and no barrier.
+// SHT = 3 (last forward radix E): as 2, with each thread taking Z_{N-k}
+// for its bins k from a lane of its own wavefront (ds_bpermute), so that
+// the R2C unpack needs no LDS buffer and no barrier.  Lines of at most 64
+// threads lie in one wavefront anyway; lines of 128 run the forward
+// transforms' last stage in mirror_order to make it so.
 template <class PI, class PF, int U, int MODE, int W, typename R, int BPC = 0, bool WS = false, int SHT = 0>
 __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
 {
@@ -313,12 +314,15 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
         lds_sync<WS>();
     };
 
-    // SHT = 3: v holds Z[b + m G], b = mirror_order(t), m < E; the partner
-    // lane (bins G - b) holds Z[N - b - m G] in slot E - 1 - m
+    // SHT = 3: v holds Z[b + m G], m < E (b = mirror_order(t) for lines of
+    // 128 threads, t otherwise); the lane holding bins G - b has
+    // Z[N - b - m G] in slot E - 1 - m
     auto fwd_store_mir = [&](int p, const cpx<R>(&v)[E]) {
-        static_assert(SHT != 3 || (G == 128 && PF::RL == E && N == E * G && K < 3 * G), "mirrored unpack: 128-thread lines, last radix E");
-        const int b = mirror_order(t);
-        const int pl = 4 * mirror_lane((G - b) & (G - 1));
+        static_assert(SHT != 3 || ((G == 128 || (G <= 64 && 64 % G == 0)) && PF::RL == E && N == E * G && K < 3 * G),
+                      "register unpack: lines of 128 threads or inside one wavefront, last radix E");
+        const int b = G == 128 ? mirror_order(t) : t;
+        const int pg = (G - b) & (G - 1);  // butterfly with the mirrored bins
+        const int pl = 4 * (G == 128 ? mirror_lane(pg) : (int)(threadIdx.x & 63) - t + pg);
         auto bp = [&](R x) {
             if constexpr (sizeof(R) == 4) {
                 return __builtin_bit_cast(R, __builtin_amdgcn_ds_bpermute(pl, __builtin_bit_cast(int, x)));
@@ -373,7 +377,7 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
             for (int i = 0; i < E; ++i) o[i] = {za[i].x * zb[i].x, za[i].y * zb[i].y};
         };
         if constexpr (SHT == 3) {
-            auto fwd = [&](auto& w) { PF::template run_n<-1, 1, 0, true, WS, true>(w, t, my, twF); };
+            auto fwd = [&](auto& w) { PF::template run_n<-1, 1, 0, true, WS, G == 128>(w, t, my, twF); };
             {
                 cpx<R> w[1][E];
                 mul(w[0], z[0], z[0]);

@@ -24,7 +24,8 @@ SizeKernels make32()
     add_x_sht<PB, PBR, 8, 1, R, false, 2>(k, "G16 r8.8.2 U8 sht2");
     add_x_sht<PS, PS, 8, 1, R>(k, "G16 r8.2.8 U8 sht");
     add_x_sht<PS, PS, 8, 1, R, false, 2>(k, "G16 r8.2.8 U8 sht2");
-    add_x_sht<PS, PS, 4, 1, R, false, 2>(k, "G16 r8.2.8 U4 sht2");
+    add_x_sht<PS, PS, 8, 1, R, true, 3>(k, "G16 r8.2.8 U8 wave sht2 mirror");
+    add_x_sht<PS, PS, 8, 1, R, false, 3>(k, "G16 r8.2.8 U8 sht2 mirror");
     add_x_sht<PS, PS, 8, 1, R, true, 2>(k, "G16 r8.2.8 U8 wave sht2");
     add_x<PC, PCR, 4, 1, R>(k, "G32 r4.4.4.2 U4");
     add_x<PA, Plan<128, 8, Radices<8, 16>>, 16, 1, R>(k, "G8 r16.8 U16");

@@ -30,7 +30,7 @@ SizeKernels make32()
     add_x_sht<PA, PA, 4, 3, R, true>(k, "G64 r8.8.8 U4 wave w3 sht");
     add_x_sht<PA, PA, 4, 3, R, true, 2>(k, "G64 r8.8.8 U4 wave w3 sht2");
     add_x_sht<PA, PA, 2, 3, R, true, 2>(k, "G64 r8.8.8 U2 wave w3 sht2");
-    add_x_sht<PA, PA, 1, 3, R, true, 2>(k, "G64 r8.8.8 U1 wave w3 sht2");
+    add_x_sht<PA, PA, 4, 3, R, true, 3>(k, "G64 r8.8.8 U4 wave w3 sht2 mirror");
     add_x_ws<PB, PBR, 4, 1, R>(k, "G32 r16.8.4 U4 wave");
     add_xh<PH, 8, 1, R>(k, "half G32 r8.4.8 U8");
     add_f3<PA, 4, 0, 1, R>(k, "G64 r8.8.8 T4");

@@ -98,35 +98,41 @@ def test_mirror_order_is_a_permutation_with_mirror_pairs_in_one_wavefront():
         assert mirror_lane(partner) == tp % 64
 
 
-@pytest.mark.parametrize("N, radices", [(1024, (8, 4, 4, 8))])
-def test_mirrored_last_stage_gives_each_bin_its_mirror_in_a_partner_slot(N, radices):
-    """Run the Stockham index maps with the last stage on butterfly
-    mirror_order(t): thread t then holds X[b + 128 m] in slot m, and bin
-    N - (b + 128 m) sits in slot E - 1 - m of the partner lane (b != 0) or in
-    slot (E - m) mod E of the thread itself (b = 0)."""
-    G = 128
+@pytest.mark.parametrize("N, G, radices", [(1024, 128, (8, 4, 4, 8)), (512, 64, (8, 8, 8)), (128, 16, (8, 2, 8))])
+def test_register_unpack_finds_each_mirror_bin_in_its_wavefront(N, G, radices):
+    """The last stage runs butterfly b = mirror_order(t) (lines of 128
+    threads) or b = t (lines inside one wavefront): thread t then holds
+    X[b + G m] in slot m, and bin N - (b + G m) sits in slot E - 1 - m of
+    the lane the kernel computes for butterfly (G - b) mod G (b != 0), or in
+    slot (E - m) mod E of the thread itself (b = 0).  Several lines share a
+    wavefront when G < 64; the block's thread index is u G + t for line u."""
     E = N // G
-    R = radices[-1]
-    assert R == E
-    held = {}
-    for t in range(G):
-        b = mirror_order(t)
-        for m in range(R):
-            held[b + m * (N // R)] = (t, m)
-    assert sorted(held) == list(range(N))
+    assert radices[-1] == E and E * G == N
     K = (N - 1) // 3
-    for t in range(G):
-        b = mirror_order(t)
-        lane = t % 64
-        for m in range(3):
-            k = b + m * G
-            if k > K:
-                continue
-            src_t, src_slot = held[(N - k) % N]
-            if b == 0:
-                assert (src_t, src_slot) == (t, (E - m) % E)
-            else:
-                assert src_t // 64 == t // 64
-                assert src_t % 64 == mirror_lane((G - b) % G)
-                assert src_slot == E - 1 - m
-        assert lane == mirror_lane(b)
+    assert K < 3 * G
+    order = (lambda t: mirror_order(t)) if G == 128 else (lambda t: t)
+    lines = max(1, 64 // G) * 2
+    held = {}
+    for u in range(lines):
+        for t in range(G):
+            b = order(t)
+            for m in range(E):
+                held[(u, b + m * G)] = (u * G + t, m)
+    for u in range(lines):
+        assert sorted(k for (uu, k) in held if uu == u) == list(range(N))
+        for t in range(G):
+            tid = u * G + t
+            b = order(t)
+            pg = (G - b) % G
+            lane = mirror_lane(pg) if G == 128 else (tid & 63) - t + pg
+            for m in range(3):
+                k = b + m * G
+                if k > K:
+                    continue
+                src_tid, src_slot = held[(u, (N - k) % N)]
+                if b == 0:
+                    assert (src_tid, src_slot) == (tid, (E - m) % E)
+                else:
+                    assert src_tid // 64 == tid // 64, (u, t, m)  # same wavefront
+                    assert src_tid % 64 == lane
+                    assert src_slot == E - 1 - m
