@@ -37,6 +37,12 @@ SizeKernels make32()
     add_f3<PB, 8, 0, 1, R>(k, "G16 r8.8.2 T8");
     add_f3<PA, 16, 0, 1, R>(k, "G8 r16.8 T16");
     add_f3<PC, 8, 0, 1, R>(k, "G32 r4.4.4.2 T8");
+    add_f3<PB, 16, 0, 1, R, 1>(k, "G16 r8.8.2 T16 prefetch");
+    add_f3<PS, 16, 0, 1, R, 1>(k, "G16 r8.2.8 T16 prefetch");
+    add_f3<PS, 16, 0, 1, R, 1, 1>(k, "G16 r8.2.8 T16 prefetch db");
+    add_f3<PS, 8, 0, 1, R, 1>(k, "G16 r8.2.8 T8 prefetch");
+    add_f3<PS, 32, 0, 1, R, 1>(k, "G16 r8.2.8 T32 prefetch");
+    add_f3<PS, 64, 0, 1, R, 1>(k, "G16 r8.2.8 T64 prefetch");
     // the adjoint x pass holds eight fields per thread: four elements each
     k.x_adj = launch_x<PC, PCR, 4, X_ADJ, 1, R>;
     return k;

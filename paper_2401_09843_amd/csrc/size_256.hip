@@ -31,6 +31,8 @@ SizeKernels make32()
     add_f3<PB, 16, 0, 1, R>(k, "G32 r8.8.4 T16");
     add_f3<PA, 16, 0, 1, R>(k, "G16 r16.16 T16");
     add_f3<PC, 4, 0, 1, R>(k, "G64 r4.4.4.4 T4");
+    add_f3<PB, 16, 0, 1, R, 1>(k, "G32 r8.8.4 T16 prefetch");
+    add_f3<PB, 32, 0, 1, R, 1>(k, "G32 r8.8.4 T32 prefetch");
     return k;
 }
 

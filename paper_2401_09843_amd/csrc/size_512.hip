@@ -37,6 +37,9 @@ SizeKernels make32()
     add_f3<PA, 8, 1, 1, R>(k, "G64 r8.8.8 T8 split");
     add_f3<PC, 4, 0, 1, R>(k, "G128 r4.4.4.4.2 T4");
     add_f3<PB, 8, 0, 1, R>(k, "G32 r16.8.4 T8");
+    add_f3<PA, 8, 0, 1, R, 1>(k, "G64 r8.8.8 T8 prefetch");
+    add_f3<PA, 16, 0, 1, R, 1>(k, "G64 r8.8.8 T16 prefetch");
+    add_f3<PA, 8, 0, 1, R, 1, 1>(k, "G64 r8.8.8 T8 prefetch db");
     return k;
 }
 

@@ -27,6 +27,9 @@ SizeKernels make32()
     add_f3<PA, 8, 0, 1, R>(k, "G8 r8.8 T8");
     add_f3<PA, 32, 0, 1, R>(k, "G8 r8.8 T32");
     add_f3<PB, 8, 0, 1, R>(k, "G16 r4.4.4 T8");
+    add_f3<PA, 32, 0, 1, R, 1>(k, "G8 r8.8 T32 prefetch");
+    add_f3<PA, 64, 0, 1, R, 1>(k, "G8 r8.8 T64 prefetch");
+    add_f3<PA, 128, 0, 1, R, 1>(k, "G8 r8.8 T128 prefetch");
     return k;
 }
 
