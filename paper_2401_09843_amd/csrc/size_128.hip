@@ -19,6 +19,10 @@ SizeKernels make32()
     add_col<PA, 32, 0, 1, R>(k, "G8 r16.8 T32");
     add_col<PA, 64, 0, 1, R>(k, "G8 r16.8 T64");
     add_col<PC, 16, 0, 1, R>(k, "G32 r4.4.4.2 T16");
+    add_col<PS, 32, 0, 1, R>(k, "G16 r8.2.8 T32");
+    add_col<PS, 64, 0, 1, R>(k, "G16 r8.2.8 T64");
+    add_col<PA, 64, 1, 1, R>(k, "G8 r16.8 T64 split");
+    add_col<PA, 128, 1, 1, R>(k, "G8 r16.8 T128 split");
     add_x<PB, PBR, 8, 1, R>(k, "G16 r8.8.2 U8");
     add_x_sht<PB, PBR, 8, 1, R>(k, "G16 r8.8.2 U8 sht");
     add_x_sht<PB, PBR, 8, 1, R, false, 2>(k, "G16 r8.8.2 U8 sht2");
