@@ -25,6 +25,23 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def edge_errors(got, ref, n):
+    """Per-mode maximum (relative to the largest mode) and the relative L2
+    error on the cutoff faces and on the k_x = 0 plane, where an error in a
+    variant's Hermitian handling or truncation could hide under a
+    whole-array norm."""
+    K = (n - 1) // 3
+    kz = np.abs(np.fft.fftfreq(n, 1.0 / n))[:, None, None]
+    ky = np.abs(np.fft.fftfreq(n, 1.0 / n))[None, :, None]
+    kx = np.arange(n // 2 + 1)[None, None, :]
+    faces = ((kz == K) | (ky == K) | (kx == K)) & (kz <= K) & (ky <= K) & (kx <= K)
+    faces = np.broadcast_to(faces, got.shape[1:])
+    plane0 = np.zeros(got.shape[1:], dtype=bool)
+    plane0[:, :, 0] = True
+    e_max = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    return e_max, rel(got[:, faces], ref[:, faces]), rel(got[:, plane0], ref[:, plane0])
+
+
 def each_variant(S, n):
     for p in range(NPASS):
         for v in range(S.variant_count(n, p)):
@@ -46,6 +63,8 @@ def test_variants_small(ns, orc, n, dtype):
         print("n=%d %s pass %d variant %d" % (n, dtype, p, v), flush=True)
         got = S.rhs(x).cpu().numpy().astype(np.complex128)
         assert rel(got, ref) <= tol, (p, v)
+        e_max, e_face, e_plane = edge_errors(got, ref, n)
+        assert e_max <= tol and e_face <= 10 * tol and e_plane <= 10 * tol, (p, v, e_max, e_face, e_plane)
 
 
 def _support(modes, K):
