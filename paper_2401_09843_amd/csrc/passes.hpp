@@ -459,7 +459,10 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
         // elements it wrote (the strain comes out of the same plan at the
         // same positions), so no barrier is needed.
         constexpr bool PARK = xadj_park<PI, PF, U, R>();
-        cpx<R> a0[E], a1[E], a2[E], v[E];
+        cpx<R> aa[3][E], v[E];
+        cpx<R>(&a0)[E] = aa[0];
+        cpx<R>(&a1)[E] = aa[1];
+        cpx<R>(&a2)[E] = aa[2];
         cpx<R> ur[PARK ? 1 : 3][E];
         cpx<R>* uv = twI + (SAME ? PI::tw_len : PI::tw_len + PF::tw_len) + u * 3 * N;
         if constexpr (PARK) {
@@ -498,9 +501,17 @@ __global__ void __launch_bounds__(PI::G* U, W) k_xline(XArgs a)
                 default: fma2(a1, v, 2, 2); fma2(a2, v, 1, 2); break;
             }
         }
-        fwd_store(0, a0, std::false_type{});
-        fwd_store(1, a1, std::false_type{});
-        fwd_store(2, a2, std::false_type{});
+        if constexpr (SHT >= 3) {
+            // the three forward transforms grouped, then the register unpack
+            PF::template run_n<-1, 1, 0, true, WS, G == 128>(aa, t, my, twF);
+            fwd_store_mir(0, aa[0]);
+            fwd_store_mir(1, aa[1]);
+            fwd_store_mir(2, aa[2]);
+        } else {
+            fwd_store(0, a0, std::false_type{});
+            fwd_store(1, a1, std::false_type{});
+            fwd_store(2, a2, std::false_type{});
+        }
     } else if constexpr (MODE == X_INV3) {
         cpx<R> v[E];
         for (int c = 0; c < 3; ++c) {

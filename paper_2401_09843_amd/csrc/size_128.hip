@@ -47,8 +47,9 @@ SizeKernels make32()
     add_f3<PS, 8, 0, 1, R, 1>(k, "G16 r8.2.8 T8 prefetch");
     add_f3<PS, 32, 0, 1, R, 1>(k, "G16 r8.2.8 T32 prefetch");
     add_f3<PS, 64, 0, 1, R, 1>(k, "G16 r8.2.8 T64 prefetch");
-    // the adjoint x pass holds eight fields per thread: four elements each
-    k.x_adj = launch_x<PC, PCR, 4, X_ADJ, 1, R>;
+    // the adjoint x pass holds eight fields per thread: four elements each;
+    // its three forward transforms grouped, with the register unpack
+    k.x_adj = launch_x<PC, PCR, 4, X_ADJ, 1, R, 0, false, 3>;
     return k;
 }
 
@@ -61,8 +62,9 @@ SizeKernels make64()
     add_x<PC, PCR, 4, 1, R>(k, "G32 r4.4.4.2 U4");
     add_f3<PB, 4, 0, 1, R>(k, "G16 r8.8.2 T4");
     add_f3<PC, 4, 0, 1, R>(k, "G32 r4.4.4.2 T4");
-    // the adjoint x pass holds eight fields per thread: four elements each
-    k.x_adj = launch_x<PC, PCR, 4, X_ADJ, 1, R>;
+    // the adjoint x pass holds eight fields per thread: four elements each;
+    // its three forward transforms grouped, with the register unpack
+    k.x_adj = launch_x<PC, PCR, 4, X_ADJ, 1, R, 0, false, 3>;
     return k;
 }
 }  // namespace
